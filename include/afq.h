@@ -1,0 +1,173 @@
+/*
+ * afq.h -- C ABI of the MI355X phaseless-AFQMC walker-step library.
+ *
+ * Method: Sukurma et al., "Towards Large-Scale AFQMC Calculations: Large Time
+ * Step Auxiliary-Field Quantum Monte Carlo" (arXiv 2403.02542).  The library
+ * runs the batched walker step of Sec. II.A with the Split-2 propagator of
+ * Sec. III.B, the Krylov (Sec. IV.C) or Taylor (Sec. IV.A) exponential, the
+ * capping rules of Sec. V.A-D and the local energy of Eq. (eloc), entirely
+ * in hand-written HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Closed shell: N_alpha == N_beta == N.  One complex M x N orbital matrix
+ *    per walker carries both spins; <Psi_T|Phi> = det(Psi_T^T Phi)^2.
+ *  - Matrices at the boundary are row-major.  Complex arrays are interleaved
+ *    (re, im) float64 pairs, i.e. the layout of complex128 / torch.cdouble.
+ *  - `ptr_is_device` = 0: pointers are host memory and the call copies
+ *    synchronously.  = 1: pointers are device memory on the context's device;
+ *    the call enqueues on the context stream and returns (the caller keeps
+ *    the buffers alive until the stream has passed the call).
+ *  - Inputs are copied: the caller may free host inputs when a call returns.
+ *  - The context owns all device state it allocates; nothing is shared
+ *    between contexts.  One context per host thread.
+ *  - Errors: every call returns an afq_status; no C++ exception crosses the
+ *    boundary.  On error the context is unchanged and afq_last_error()
+ *    describes the failure.
+ */
+#ifndef AFQ_H
+#define AFQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct afq_ctx afq_ctx;
+typedef int32_t afq_status;
+
+enum {
+  AFQ_OK = 0,
+  AFQ_EINVAL = 1,   /* bad argument: shape, range, asymmetric input, ...       */
+  AFQ_ENOMEM = 2,   /* device allocation failed                                 */
+  AFQ_EDEVICE = 3,  /* HIP runtime error (text in afq_last_error)               */
+  AFQ_ESTATE = 4,   /* call out of order (e.g. propagate before init_trial)     */
+  AFQ_ENUMERIC = 5  /* every walker of a system is non-finite                   */
+};
+enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1 };
+enum { AFQ_PREC_FP64 = 0, AFQ_PREC_MIXED = 1 };
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on, or NULL for a stream owned by the context (default priority). */
+afq_status afq_create(afq_ctx** out, int device, void* hip_stream);
+void afq_destroy(afq_ctx* ctx);
+/* Text of the last error on this context; valid until the next call. */
+const char* afq_last_error(const afq_ctx* ctx);
+
+/* Hamiltonian of Eq. (mbham) in Cholesky form, Sec. II.A:
+ *   h      M x M one-body matrix, symmetric (checked to 1e-12 relative),
+ *   L      n_chol x M x M Cholesky vectors, each symmetric (checked),
+ *          <pq|rs> = sum_g L[g,p,r] L[g,q,s],
+ *   e_core constant energy.
+ * Returns a system id (0, 1, ...) in *sys_id.  Several systems may live in
+ * one context; they are propagated together by afq_propagate_batch. */
+afq_status afq_init_hamiltonian(afq_ctx* ctx, int64_t M, int64_t n_chol,
+                                const double* h, const double* L, double e_core,
+                                int ptr_is_device, int32_t* sys_id);
+
+/* Trial determinant Psi_T (Sec. II.A): M x n_alpha real, orthonormal
+ * columns (checked to 1e-10).  n_beta must equal n_alpha (closed shell).
+ * Precomputes the mean-field shift Lbar_g (Eq. force_shift), the one-body
+ * matrix H1 = h - 1/2 sum_g L_g L_g + sum_g Lbar_g L_g that accompanies the
+ * shifted HS transform, its eigendecomposition for the exact half-step
+ * exp(-tau H1/2) of Sec. III.B, the half-rotated Psi_T^T h and Psi_T^T L_g,
+ * and the trial energy E_L(Psi_T). */
+afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha,
+                          int64_t n_beta, const double* psi_t, int ptr_is_device);
+
+/* Walker store of a system (Eq. wavefun_rep): n_walkers determinants set to
+ * phi0 (complex128, n_walkers x M x N) or, if phi0 is NULL, to Psi_T; weights
+ * 1; log-overlaps log det(Psi_T^T Phi). */
+afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers,
+                            const void* phi0, int ptr_is_device);
+
+typedef struct {
+  double tau;            /* imaginary time step                                  */
+  int32_t exp_method;    /* AFQ_EXP_KRYLOV or AFQ_EXP_TAYLOR                   */
+  int32_t exp_order;     /* k: Krylov dimension / Taylor order (1..16)            */
+  int32_t reorth_every;  /* QR after global step t when (t+1) % reorth_every == 0 */
+  int32_t precision;     /* AFQ_PREC_FP64 or AFQ_PREC_MIXED                       */
+  int32_t n_steps;       /* steps to run                                         */
+  int32_t energy_every;  /* 1 = local energy every step (0 is read as 1)         */
+  double e0;             /* energy shift E0; NaN = trial energy (fixed)          */
+  uint64_t seed;         /* Philox key word 0 (word 1 is the system id)          */
+  uint64_t step0;        /* global index of the first step (RNG counter, QR)     */
+  const double* fields;  /* optional DEVICE array [n_steps][W][n_chol] of N(0,1)
+                            fields (single-system calls only); NULL = Philox     */
+  double* energies_out;  /* optional DEVICE array [n_sys][n_steps][2]:
+                            (sum_w W E_L capped, sum_w W) per step               */
+} afq_prop_params;
+
+/* Run n_steps Split-2 walker steps on every walker of the listed systems.
+ * Per step and walker (Sec. II.A, III.B, IV, V): force bias from the current
+ * mixed Green's function with the |f| < 1 cap; shifted fields; operator
+ * A = i sqrt(tau) sum_g (x_g - f_g) L_g; Phi <- B exp(A) B Phi with
+ * B = exp(-tau H1/2); overlap ratio, hybrid energy and phaseless weight with
+ * the reweighting cap; QR reorthonormalisation on schedule; local energy with
+ * the energy window.  Enqueued on the context stream; no host synchronisation
+ * inside the loop.  A walker whose new overlap or Green's function is not
+ * finite, or whose reorthonormalisation fails (numerically rank-deficient
+ * orbitals), is frozen: its state is held, its weight set to 0 and it is
+ * counted (not an error; see afq_get_counters). */
+afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys,
+                               const afq_prop_params* params);
+
+/* Local energy of every walker (Eq. eloc) at its current determinant:
+ * eloc_out complex128 [W].  The Coulomb vector ell_g = <Lhat_g>_mixed,
+ * complex128 [W][n_chol], is written to ell_out if it is not NULL. */
+afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, double* eloc_out,
+                                  double* ell_out, int ptr_is_device);
+
+/* Adjoint of the local energy at fixed walkers and fixed Psi_T:
+ * grad_h[M][M]      = sum_w dE_dEL[w] d Re E_L^w / d h,
+ * grad_L[g][M][M]   = sum_w dE_dEL[w] d Re E_L^w / d L_g,
+ * with respect to unconstrained matrix entries (symmetrise for symmetric
+ * parameters).  dE_dEL is real [W]. */
+afq_status afq_local_energy_adjoint(afq_ctx* ctx, int32_t sys_id, const double* dE_dEL,
+                                    double* grad_h, double* grad_L, int ptr_is_device);
+
+/* Adjoint of the Coulomb vector (force bias without its affine map):
+ * grad_L[g][M][M] = sum_w Re(d_ell[w][g]) d Re ell_g^w / d L_g
+ *                 + Im(d_ell[w][g]) d Im ell_g^w / d L_g;  d_ell complex128. */
+afq_status afq_force_bias_adjoint(afq_ctx* ctx, int32_t sys_id, const double* d_ell,
+                                  double* grad_L, int ptr_is_device);
+
+/* Read / write the walker store: phi complex128 [W][M][N], weight [W],
+ * log_ovlp complex128 [W] (log det(Psi_T^T Phi), one spin), alive int32 [W].
+ * Any output pointer may be NULL.  afq_set_walkers recomputes the Green's
+ * functions and the log-overlaps of the given determinants. */
+afq_status afq_get_walkers(afq_ctx* ctx, int32_t sys_id, void* phi, double* weight,
+                           double* log_ovlp, int32_t* alive, int ptr_is_device);
+afq_status afq_set_walkers(afq_ctx* ctx, int32_t sys_id, const void* phi,
+                           const double* weight, int ptr_is_device);
+
+/* Auxiliary fields of one step from the library's Philox4x64-10 generator:
+ * out[w][g], n_walkers x n_chol float64 (device pointer). */
+afq_status afq_fill_fields(afq_ctx* ctx, uint64_t seed, uint64_t sys_id, uint64_t step,
+                           int64_t n_walkers, int64_t n_chol, double* out_dev);
+
+/* Per-system diagnostics of the last afq_propagate_batch call (synchronises):
+ * out[0] live walkers at the last measured step, out[1] capped force-bias
+ * components, out[2] Krylov happy breakdowns, out[3] walkers frozen. */
+afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4);
+
+/* Per-phase timing with HIP events on the context stream.  While enabled,
+ * afq_propagate_batch records an event pair around every phase of every
+ * step; afq_profile_read synchronises, returns the accumulated milliseconds
+ * and launch counts of the first n phases (AFQ_PH_*) and clears them. */
+enum {
+  AFQ_PH_FIELDS = 0, AFQ_PH_FORCE_BIAS, AFQ_PH_OPBUILD, AFQ_PH_ONEBODY, AFQ_PH_EXPONENTIAL,
+  AFQ_PH_OVERLAP, AFQ_PH_WEIGHT, AFQ_PH_QR, AFQ_PH_EXCHANGE, AFQ_PH_ENERGY, AFQ_PH_COUNT
+};
+afq_status afq_profile(afq_ctx* ctx, int enable);
+afq_status afq_profile_read(afq_ctx* ctx, double* ms_out, int64_t* launches_out, int n);
+
+/* Wait for all work enqueued on the context stream. */
+afq_status afq_sync(afq_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFQ_H */

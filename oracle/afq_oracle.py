@@ -297,7 +297,8 @@ def phaseless_factor(p: Prepared, e_h: complex, dtheta: float) -> float:
     """exp(-tau (Re E_H - E0)) max(0, cos dtheta)   (Eq. phaseless), with the
     reweighting cap of Sec. V.B: a factor of 10 or more becomes 0 (Reading:
     the cap applies to the magnitude, before the cosine)."""
-    m = math.exp(-p.tau * (e_h.real - p.e0))
+    arg = -p.tau * (e_h.real - p.e0)
+    m = math.exp(arg) if arg < 700.0 else math.inf
     if not m < 10.0:
         m = 0.0
     return m * max(0.0, math.cos(dtheta))

@@ -1,0 +1,196 @@
+// Device-side building blocks shared by the walker-step kernels (gfx950).
+//
+//  * complex helpers on (re, im) double pairs,
+//  * wavefront (64-lane) and workgroup reductions in a fixed order, so every
+//    run of a kernel gives bitwise the same sums,
+//  * an LDS-staged tile engine around the FP64 matrix-core instruction
+//    v_mfma_f64_16x16x4f64.  Operand layout of that instruction on gfx950
+//    (measured): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+//    accumulator element i of lane l is C[4 i + l / 16][l % 16].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define AFQ_DEV __device__ __forceinline__
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+struct cplx {
+  double re, im;
+};
+
+AFQ_DEV cplx cmake(double r, double i) { return cplx{r, i}; }
+AFQ_DEV cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
+AFQ_DEV cplx csub(cplx a, cplx b) { return cplx{a.re - b.re, a.im - b.im}; }
+AFQ_DEV cplx cmul(cplx a, cplx b) {
+  return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+AFQ_DEV cplx cmulc(cplx a, cplx b) {
+  return cplx{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+AFQ_DEV cplx cscale(cplx a, double s) { return cplx{a.re * s, a.im * s}; }
+AFQ_DEV double cabs2(cplx a) { return a.re * a.re + a.im * a.im; }
+AFQ_DEV cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, d = b.re + b.im * r;
+    return cplx{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  } else {
+    double r = b.re / b.im, d = b.re * r + b.im;
+    return cplx{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+  }
+}
+AFQ_DEV cplx clog(cplx a) { return cplx{0.5 * log(cabs2(a)), atan2(a.im, a.re)}; }
+
+// ---------------------------------------------------------------- reductions
+
+AFQ_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+AFQ_DEV double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum over the workgroup; every thread gets the result.  `red` holds at
+// least blockDim.x / 64 doubles of LDS.  Fixed order: waves, then slots.
+AFQ_DEV double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------- MFMA tiles
+
+AFQ_DEV d4_t mfma_f64(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Tile engine: a 256-thread workgroup computes C[r][c] = sum_k A[r][k] B[c][k]
+// for r < 32 MT, c < 32 NT.  The four waves form a 2 x 2 grid over the 16 x 16
+// MFMA tiles (see wave_split); each wave holds at most MT x NT of them.
+// K is consumed in chunks of BK = 16 staged in LDS as As[r][k], Bs[c][k] with
+// a row pitch of 17 doubles (conflict-free fragment reads).
+constexpr int kBK = 16;
+constexpr int kLDK = kBK + 1;
+
+template <int MT, int NT>
+struct TileAcc {
+  d4_t c[MT][NT];
+  AFQ_DEV void zero() {
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) c[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+  }
+};
+
+template <int MT, int NT>
+struct TileShape {
+  static constexpr int ROWS = 32 * MT;
+  static constexpr int COLS = 32 * NT;
+  static constexpr int LDS_DOUBLES = (ROWS + COLS) * kLDK;
+};
+
+// Work split of a tile among the four waves (2 x 2 grid): the TR valid row
+// tiles are divided as evenly as possible between the two wave rows, and the
+// TC valid column tiles between the two wave columns.
+struct WaveSplit {
+  int rt0, mtv, ct0, ntv;
+};
+template <int MT, int NT>
+AFQ_DEV WaveSplit wave_split(int nrows, int ncols) {
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int TR = (nrows + 15) >> 4, TC = (ncols + 15) >> 4;
+  const int hr = (TR + 1) >> 1, hc = (TC + 1) >> 1;
+  WaveSplit s;
+  s.rt0 = wr * hr;
+  s.mtv = min(MT, max(0, min(hr, TR - s.rt0)));
+  s.ct0 = wc * hc;
+  s.ntv = min(NT, max(0, min(hc, TC - s.ct0)));
+  return s;
+}
+
+// One BK chunk of MFMAs from LDS.
+template <int MT, int NT>
+AFQ_DEV void tile_mma_chunk(const double* As, const double* Bs, TileAcc<MT, NT>& acc,
+                            const WaveSplit& ws) {
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < kBK; kk += 4) {
+    double a[MT], b[NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) a[i] = As[((ws.rt0 + i) * 16 + lr) * kLDK + kk + lk];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) b[j] = Bs[((ws.ct0 + j) * 16 + lr) * kLDK + kk + lk];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+      if (i < ws.mtv) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          if (j < ws.ntv) acc.c[i][j] = mfma_f64(a[i], b[j], acc.c[i][j]);
+      }
+    }
+  }
+}
+
+// Row / column (within the tile) of accumulator element e of tile (i, j).
+AFQ_DEV int acc_row(const WaveSplit& ws, int i, int e) {
+  return (ws.rt0 + i) * 16 + 4 * e + ((threadIdx.x & 63) >> 4);
+}
+AFQ_DEV int acc_col(const WaveSplit& ws, int j) {
+  return (ws.ct0 + j) * 16 + (threadIdx.x & 15);
+}
+
+// Full K loop.  fillA(k0, As) / fillB(k0, Bs) stage one chunk (zero beyond
+// the valid ranges); both are called by all threads.  Requires
+// ceil(nrows / 16) <= 2 MT and ceil(ncols / 16) <= 2 NT.
+template <int MT, int NT, class FillA, class FillB>
+AFQ_DEV void tile_gemm(int K, const WaveSplit& ws, FillA fillA, FillB fillB, double* As,
+                       double* Bs, TileAcc<MT, NT>& acc) {
+  for (int k0 = 0; k0 < K; k0 += kBK) {
+    __syncthreads();
+    fillA(k0, As);
+    fillB(k0, Bs);
+    __syncthreads();
+    tile_mma_chunk<MT, NT>(As, Bs, acc, ws);
+  }
+}
+
+// Staging helper: element (r, k) of a tile with ROWS rows from a functor
+// get(r, k) (only called for r < nvalid, k < K); zero elsewhere.  Consecutive
+// threads take consecutive k (operands stored with k contiguous).
+template <int ROWS, class Get>
+AFQ_DEV void stage_rows(double* S, int k0, int K, int nvalid, Get get) {
+  for (int e = threadIdx.x; e < ROWS * kBK; e += blockDim.x) {
+    const int r = e >> 4, k = e & 15;
+    double v = 0.0;
+    if (r < nvalid && k0 + k < K) v = get(r, k0 + k);
+    S[r * kLDK + k] = v;
+  }
+}
+// Same, but consecutive threads take consecutive r (operands stored with r
+// contiguous, k outer).
+template <int ROWS, class Get>
+AFQ_DEV void stage_rows_kmajor(double* S, int k0, int K, int nvalid, Get get) {
+  for (int e = threadIdx.x; e < ROWS * kBK; e += blockDim.x) {
+    const int k = e / ROWS, r = e - k * ROWS;
+    double v = 0.0;
+    if (r < nvalid && k0 + k < K) v = get(r, k0 + k);
+    S[r * kLDK + k] = v;
+  }
+}

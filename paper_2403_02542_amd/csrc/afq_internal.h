@@ -1,0 +1,132 @@
+// Internal state of the walker-step library and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+// Device arrays of one system.  Complex walker data are planar (separate
+// real and imaginary arrays); a walker's orbitals are stored orbital-major,
+// [w][j][p], so that one orbital is a contiguous M-vector.
+struct SysDev {
+  int M = 0, N = 0, G = 0, W = 0;
+  double e_core = 0.0;
+  // Hamiltonian
+  double* h = nullptr;        // [M][M]
+  double* L = nullptr;        // [G][M][M]
+  // trial
+  double* psit = nullptr;     // [N][M]   Psi_T^T
+  double* Lx = nullptr;       // [(G+1)][N][M]: Psi_T^T L_g for g < G, Psi_T^T h for g = G
+  double* lbar = nullptr;     // [G]
+  double* H1 = nullptr;       // [M][M]
+  double* Bhalf = nullptr;    // [M][M] exp(-tau H1 / 2)
+  double tau_b = -1.0;
+  double e_const = 0.0, e_trial = 0.0;
+  std::vector<double> h1_evals, h1_evecs;   // host eigendecomposition of H1
+  bool trial_ready = false;
+  // walkers
+  double *phi_re = nullptr, *phi_im = nullptr;     // [W][N][M]
+  double *phn_re = nullptr, *phn_im = nullptr;     // next-step orbitals
+  double *th_re = nullptr, *th_im = nullptr;       // Theta = Phi (Psi_T^T Phi)^-1
+  double *thn_re = nullptr, *thn_im = nullptr;
+  double* logdet = nullptr;   // [W][2]
+  double* logdet_n = nullptr; // [W][2]
+  double* weight = nullptr;   // [W]
+  int* alive = nullptr;       // [W]
+  int* bad = nullptr;         // [W] non-finite flag of the new state
+  double* qr_logr = nullptr;  // [W] log det R of the step's reorthonormalisation
+  double *ell_re = nullptr, *ell_im = nullptr;     // [W][G+1]
+  double *ex_re = nullptr, *ex_im = nullptr;       // [W][G+1]
+  double* eloc = nullptr;     // [W][2]
+  double* ecap = nullptr;     // [W]
+  double* x = nullptr;        // [W][G] fields
+  double *av_re = nullptr, *av_im = nullptr;       // [W][G]: i sqrt(tau) (x - fbar)
+  double* scal = nullptr;     // [W][4]: log I (re, im), s_mf (re, im)
+  int* ncap = nullptr;        // [W]
+  double *A_re = nullptr, *A_im = nullptr;         // [W][M][M] operator
+  double *t1_re = nullptr, *t1_im = nullptr;       // [W][N][M] scratch
+  double *t2_re = nullptr, *t2_im = nullptr;
+  double *t3_re = nullptr, *t3_im = nullptr;
+  int kmax = 0;
+  double *kb_re = nullptr, *kb_im = nullptr;       // [W][N][kmax][M] Krylov basis
+  double* kh = nullptr;       // [W][N][kmax][kmax][2] Hessenberg
+  double* kbeta = nullptr;    // [W][N]
+  int* kdim = nullptr;        // [W][N]
+  double* oinv = nullptr;     // [W][N][N][2]
+  double* est = nullptr;      // [2] estimator scratch
+  int* counters = nullptr;    // [4] device counters of the last propagate call
+  std::vector<void*> walker_allocs;
+};
+
+// ------------------------------------------------------------------ launchers
+// Every launcher enqueues on `st` and returns hipGetLastError().
+
+// Generic strided batched GEMM for set-up work (FP64 MFMA):
+// C[b](r, c) = alpha * sum_k A(b, r, k) B(b, c, k) + beta * C[b](r, c), with
+// A(b, r, k) = A[b sAb + r sAr + (k / kin) sAkb + (k % kin) sAk] and
+// B(b, c, k) = B[b sBb + c sBc + (k / kin) sBkb + (k % kin) sBk].
+struct GemmArgs {
+  const double* A; int64_t sAb, sAr, sAk, sAkb;
+  const double* B; int64_t sBb, sBc, sBk, sBkb;
+  double* C; int64_t sCb, sCr, sCc;
+  int R, Cn, K, kin, batch;
+  double alpha, beta;
+};
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+
+hipError_t launch_fields(uint64_t seed, uint64_t sid, uint64_t step, int W, int G, double* out,
+                         hipStream_t st);
+hipError_t launch_lbar(const SysDev& s, hipStream_t st);
+hipError_t launch_axpy_L(const SysDev& s, const double* coef, double alpha, double* out,
+                         hipStream_t st);
+hipError_t launch_force_bias(SysDev& s, const double* x, double tau, hipStream_t st);
+hipError_t launch_opbuild(SysDev& s, hipStream_t st);
+hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
+                          double* out_im, hipStream_t st);
+// Krylov exponential of the operator on every orbital: out = krylov_k(A, in);
+// wv is a [W][N][M] scratch pair.
+hipError_t launch_krylov(SysDev& s, int k, const double* in_re, const double* in_im,
+                         double* out_re, double* out_im, double* wv_re, double* wv_im,
+                         hipStream_t st);
+// Taylor exponential: out = sum_{n<=k} A^n in / n!; s1, s2 are scratch pairs.
+hipError_t launch_taylor(SysDev& s, int k, const double* in_re, const double* in_im,
+                         double* out_re, double* out_im, double* s1_re, double* s1_im,
+                         double* s2_re, double* s2_im, hipStream_t st);
+// Overlap, log det and Theta of (phi_re, phi_im) for W walkers.
+hipError_t launch_overlap(SysDev& s, int W, const double* ph_re, const double* ph_im,
+                          double* logdet_out, double* th_re, double* th_im, int* bad,
+                          hipStream_t st);
+// Weight update; qr_logr (nullable) holds the log det R of this step's QR.
+hipError_t launch_weight(SysDev& s, double tau, double e0, const double* qr_logr,
+                         hipStream_t st);
+// Reorthonormalisation of (ph_re, ph_im) in place; writes qr_logr[W] and
+// marks walkers whose factorisation fails in s.bad.
+hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st);
+hipError_t launch_commit(SysDev& s, hipStream_t st);
+// Local energy of W walkers with Green's functions (th_re, th_im).
+hipError_t launch_exchange(SysDev& s, int W, const double* th_re, const double* th_im,
+                           double* ell_re, double* ell_im, double* ex_re, double* ex_im,
+                           hipStream_t st);
+hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* ell_im,
+                         const double* ex_re, const double* ex_im, double* eloc, double* ecap,
+                         double e0, double tau, hipStream_t st);
+hipError_t launch_estimator(SysDev& s, double* out2, hipStream_t st);
+hipError_t launch_counters(SysDev& s, int reset, hipStream_t st);
+// Boundary layout (complex128 [W][M][N], interleaved) <-> planar [W][N][M].
+hipError_t launch_to_planar(const double* in, int W, int M, int N, double* re, double* im,
+                            hipStream_t st);
+hipError_t launch_from_planar(const double* re, const double* im, int W, int M, int N,
+                              double* out, hipStream_t st);
+hipError_t launch_pack_complex(const double* re, const double* im, int64_t n, int64_t ld_in,
+                               int64_t cols, double* out, hipStream_t st);
+// Adjoint kernels.
+hipError_t launch_adjoint(SysDev& s, const double* dE, double* grad_h, double* grad_L,
+                          hipStream_t st);
+hipError_t launch_fb_adjoint(SysDev& s, const double* d_ell, double* grad_L, hipStream_t st);
+
+// Host symmetric eigensolver (cyclic Jacobi): a (n x n, row-major) is
+// destroyed; evals ascending, evecs column j = eigenvector j (row-major).
+void jacobi_eigh(int n, std::vector<double>& a, std::vector<double>& evals,
+                 std::vector<double>& evecs);

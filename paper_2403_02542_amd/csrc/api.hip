@@ -1,0 +1,788 @@
+// C ABI of the walker-step library (declared in include/afq.h): context and
+// system management, set-up of the trial, and the Split-2 step driver that
+// enqueues the kernels of one walker step after another on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "afq.h"
+#include "afq_internal.h"
+
+struct PhaseEv {
+  int phase;
+  hipEvent_t a, b;
+};
+
+struct afq_ctx {
+  bool profiling = false;
+  std::vector<PhaseEv> pending;
+  std::vector<hipEvent_t> ev_pool;
+  double ph_ms[AFQ_PH_COUNT] = {};
+  int64_t ph_n[AFQ_PH_COUNT] = {};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<SysDev*> systems;
+  std::vector<std::vector<void*>> sys_allocs;
+};
+
+namespace {
+
+afq_status fail(afq_ctx* c, afq_status code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, AFQ_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(x)                     \
+  do {                             \
+    afq_status s_ = (x);           \
+    if (s_ != AFQ_OK) return s_;   \
+  } while (0)
+
+template <class T>
+afq_status dalloc(afq_ctx* ctx, std::vector<void*>& owner, T** p, size_t n) {
+  void* q = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&q, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, AFQ_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  owner.push_back(q);
+  *p = (T*)q;
+  return AFQ_OK;
+}
+
+void free_all(std::vector<void*>& v) {
+  for (void* p : v) (void)hipFree(p);
+  v.clear();
+}
+
+// Copy n doubles from a user pointer (host or device) into device memory.
+afq_status copy_in(afq_ctx* ctx, double* dst, const double* src, size_t n, int is_dev) {
+  HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
+                        is_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+  if (!is_dev) HIPCHK(hipStreamSynchronize(ctx->stream));
+  return AFQ_OK;
+}
+afq_status copy_out(afq_ctx* ctx, void* dst, const void* src, size_t bytes, int is_dev) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, is_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        ctx->stream));
+  if (!is_dev) HIPCHK(hipStreamSynchronize(ctx->stream));
+  return AFQ_OK;
+}
+
+afq_status get_sys(afq_ctx* ctx, int32_t id, SysDev** s) {
+  if (!ctx) return AFQ_EINVAL;
+  if (id < 0 || id >= (int32_t)ctx->systems.size() || !ctx->systems[id])
+    return fail(ctx, AFQ_EINVAL, "unknown system id " + std::to_string(id));
+  *s = ctx->systems[id];
+  return AFQ_OK;
+}
+
+// max |X[b][p][q] - X[b][q][p]| and max |X| over a batch of n x n matrices
+__global__ void k_asym(const double* X, int64_t nb, int n, unsigned long long* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = nb * n * n;
+  double d = 0.0, m = 0.0;
+  if (e < tot) {
+    const int64_t b = e / ((int64_t)n * n);
+    const int r = (int)(e % ((int64_t)n * n));
+    const int p = r / n, q = r % n;
+    d = fabs(X[e] - X[b * n * n + (int64_t)q * n + p]);
+    m = fabs(X[e]);
+    if (!(d == d)) d = INFINITY;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    d = fmax(d, __shfl_xor(d, o, 64));
+    m = fmax(m, __shfl_xor(m, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(d));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+afq_status check_symmetric(afq_ctx* ctx, const double* X, int64_t nb, int n, const char* what) {
+  unsigned long long* d = nullptr;
+  HIPCHK(hipMalloc(&d, 2 * sizeof(unsigned long long)));
+  unsigned long long h[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, ctx->stream);
+  const int64_t tot = nb * n * n;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_asym, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx->stream, X, nb,
+                       n, d);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(ctx, AFQ_EDEVICE, std::string("symmetry check: ") + hipGetErrorString(e));
+  double asym, mx;
+  std::memcpy(&asym, &h[0], 8);
+  std::memcpy(&mx, &h[1], 8);
+  if (!(asym <= 1e-12 * (mx > 1.0 ? mx : 1.0)))
+    return fail(ctx, AFQ_EINVAL, std::string(what) + " is not symmetric (max asymmetry " +
+                                     std::to_string(asym) + ")");
+  return AFQ_OK;
+}
+
+// exp(-tau H1 / 2) from the host eigendecomposition.
+afq_status ensure_half_step(afq_ctx* ctx, SysDev& s, double tau) {
+  if (s.tau_b == tau && s.Bhalf) return AFQ_OK;
+  const int M = s.M;
+  std::vector<double> d(M), B((size_t)M * M, 0.0);
+  for (int k = 0; k < M; ++k) d[k] = std::exp(-0.5 * tau * s.h1_evals[k]);
+  const double* V = s.h1_evecs.data();
+  for (int p = 0; p < M; ++p)
+    for (int q = p; q < M; ++q) {
+      double acc = 0.0;
+      for (int k = 0; k < M; ++k) acc += V[(size_t)p * M + k] * d[k] * V[(size_t)q * M + k];
+      B[(size_t)p * M + q] = acc;
+      B[(size_t)q * M + p] = acc;
+    }
+  HIPCHK(hipMemcpy(s.Bhalf, B.data(), sizeof(double) * M * M, hipMemcpyHostToDevice));
+  s.tau_b = tau;
+  return AFQ_OK;
+}
+
+afq_status ensure_krylov(afq_ctx* ctx, int32_t sid, SysDev& s, int k) {
+  if (k <= s.kmax) return AFQ_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  auto& own = s.walker_allocs;
+  // the Krylov arrays are re-allocated; the old ones stay owned until destroy
+  const size_t WN = (size_t)s.W * s.N;
+  TRY(dalloc(ctx, own, &s.kb_re, WN * k * s.M));
+  TRY(dalloc(ctx, own, &s.kb_im, WN * k * s.M));
+  TRY(dalloc(ctx, own, &s.kh, WN * k * k * 2));
+  s.kmax = k;
+  (void)sid;
+  return AFQ_OK;
+}
+
+// Local energy and Coulomb vector of the current walkers (Theta in th_*).
+afq_status eval_energy(afq_ctx* ctx, SysDev& s, double e0, double tau) {
+  HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
+                         ctx->stream));
+  HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, e0, tau,
+                       ctx->stream));
+  return AFQ_OK;
+}
+
+afq_status refresh_green(afq_ctx* ctx, SysDev& s) {
+  HIPCHK(launch_overlap(s, s.W, s.phi_re, s.phi_im, s.logdet, s.th_re, s.th_im, s.bad,
+                        ctx->stream));
+  return AFQ_OK;
+}
+
+__global__ void k_init_alive(int W, const int* bad, int* alive, double* weight, int set_weight) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  alive[w] = bad[w] ? 0 : 1;
+  if (set_weight) weight[w] = 1.0;
+  if (bad[w]) weight[w] = 0.0;
+}
+
+__global__ void k_fill_trial(int W, int NM, const double* psit, double* re, double* im) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)W * NM) return;
+  re[e] = psit[e % NM];
+  im[e] = 0.0;
+}
+
+hipEvent_t take_event(afq_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around a phase when profiling is on.
+struct Phase {
+  afq_ctx* ctx;
+  int ph;
+  hipEvent_t a = nullptr;
+  Phase(afq_ctx* c, int p) : ctx(c), ph(p) {
+    if (ctx->profiling) {
+      a = take_event(ctx);
+      if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+  }
+  ~Phase() {
+    if (a) {
+      hipEvent_t b = take_event(ctx);
+      if (b) {
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->pending.push_back(PhaseEv{ph, a, b});
+      } else {
+        ctx->ev_pool.push_back(a);
+      }
+    }
+  }
+};
+
+bool reorth_due(uint64_t t, int every) { return every > 0 && ((t + 1) % (uint64_t)every) == 0; }
+
+afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_params& P, int si,
+                       int n_sys_index, double e0) {
+  hipStream_t st = ctx->stream;
+  const uint64_t t = P.step0 + (uint64_t)si;
+  const double* x = s.x;
+  if (P.fields) {
+    x = P.fields + (size_t)si * s.W * s.G;
+  } else {
+    Phase ph(ctx, AFQ_PH_FIELDS);
+    HIPCHK(launch_fields(P.seed, (uint64_t)sid, t, s.W, s.G, s.x, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_FORCE_BIAS);
+    HIPCHK(launch_force_bias(s, x, P.tau, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_OPBUILD);
+    HIPCHK(launch_opbuild(s, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_ONEBODY);
+    HIPCHK(launch_onebody(s, s.phi_re, s.phi_im, s.t1_re, s.t1_im, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_EXPONENTIAL);
+    if (P.exp_method == AFQ_EXP_KRYLOV)
+      HIPCHK(launch_krylov(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re, s.t3_im, st));
+    else
+      HIPCHK(launch_taylor(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re, s.t3_im,
+                           s.phn_re, s.phn_im, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_ONEBODY);
+    HIPCHK(launch_onebody(s, s.t2_re, s.t2_im, s.phn_re, s.phn_im, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_OVERLAP);
+    HIPCHK(launch_overlap(s, s.W, s.phn_re, s.phn_im, s.logdet_n, s.thn_re, s.thn_im, s.bad, st));
+  }
+  const bool qr = reorth_due(t, P.reorth_every);
+  if (qr) {
+    Phase ph(ctx, AFQ_PH_QR);
+    HIPCHK(launch_qr(s, s.phn_re, s.phn_im, s.qr_logr, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_WEIGHT);
+    HIPCHK(launch_weight(s, P.tau, e0, qr ? s.qr_logr : nullptr, st));
+  }
+  {
+    Phase ph(ctx, AFQ_PH_WEIGHT);
+    HIPCHK(launch_commit(s, st));
+  }
+  std::swap(s.phi_re, s.phn_re);
+  std::swap(s.phi_im, s.phn_im);
+  std::swap(s.th_re, s.thn_re);
+  std::swap(s.th_im, s.thn_im);
+  const int every = P.energy_every > 0 ? P.energy_every : 1;
+  {
+    Phase ph(ctx, AFQ_PH_EXCHANGE);
+    HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
+  }
+  if ((si + 1) % every == 0 || si + 1 == P.n_steps) {
+    Phase ph(ctx, AFQ_PH_ENERGY);
+    HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, e0, P.tau,
+                         st));
+    double* out = P.energies_out ? P.energies_out + ((size_t)n_sys_index * P.n_steps + si) * 2 : s.est;
+    HIPCHK(launch_estimator(s, out, st));
+  }
+  return AFQ_OK;
+}
+
+}  // namespace
+
+// =========================================================================== API
+
+extern "C" {
+
+afq_status afq_create(afq_ctx** out, int device, void* hip_stream) {
+  if (!out) return AFQ_EINVAL;
+  *out = nullptr;
+  afq_ctx* ctx = new (std::nothrow) afq_ctx();
+  if (!ctx) return AFQ_ENOMEM;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    delete ctx;
+    return AFQ_EDEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return AFQ_EDEVICE;
+  }
+  ctx->device = device;
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+      delete ctx;
+      return AFQ_EDEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  *out = ctx;
+  return AFQ_OK;
+}
+
+void afq_destroy(afq_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (size_t i = 0; i < ctx->systems.size(); ++i) {
+    if (ctx->systems[i]) {
+      free_all(ctx->systems[i]->walker_allocs);
+      delete ctx->systems[i];
+    }
+    free_all(ctx->sys_allocs[i]);
+  }
+  for (const PhaseEv& e : ctx->pending) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* afq_last_error(const afq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+afq_status afq_init_hamiltonian(afq_ctx* ctx, int64_t M, int64_t n_chol, const double* h,
+                                const double* L, double e_core, int ptr_is_device,
+                                int32_t* sys_id) try {
+  if (!ctx) return AFQ_EINVAL;
+  if (!h || !L || !sys_id) return fail(ctx, AFQ_EINVAL, "null pointer");
+  if (M < 1 || M > 512 || n_chol < 1 || n_chol > (int64_t)1 << 24)
+    return fail(ctx, AFQ_EINVAL, "M must be in [1, 512] and n_chol >= 1");
+  HIPCHK(hipSetDevice(ctx->device));
+  auto* s = new SysDev();
+  ctx->systems.push_back(s);
+  ctx->sys_allocs.emplace_back();
+  auto& own = ctx->sys_allocs.back();
+  const int32_t id = (int32_t)ctx->systems.size() - 1;
+  auto undo = [&](afq_status code) {
+    free_all(own);
+    delete s;
+    ctx->systems[id] = nullptr;
+    return code;
+  };
+  s->M = (int)M;
+  s->G = (int)n_chol;
+  s->e_core = e_core;
+  const size_t MM = (size_t)M * M;
+  afq_status r;
+  if ((r = dalloc(ctx, own, &s->h, MM)) != AFQ_OK) return undo(r);
+  if ((r = dalloc(ctx, own, &s->L, MM * n_chol)) != AFQ_OK) return undo(r);
+  if ((r = copy_in(ctx, s->h, h, MM, ptr_is_device)) != AFQ_OK) return undo(r);
+  if ((r = copy_in(ctx, s->L, L, MM * n_chol, ptr_is_device)) != AFQ_OK) return undo(r);
+  if ((r = check_symmetric(ctx, s->h, 1, (int)M, "h")) != AFQ_OK) return undo(r);
+  if ((r = check_symmetric(ctx, s->L, n_chol, (int)M, "L")) != AFQ_OK) return undo(r);
+  *sys_id = id;
+  return AFQ_OK;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t n_beta,
+                          const double* psi_t, int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!psi_t) return fail(ctx, AFQ_EINVAL, "null psi_t");
+  if (n_alpha != n_beta) return fail(ctx, AFQ_EINVAL, "only closed-shell trials (n_alpha == n_beta)");
+  if (n_alpha < 1 || n_alpha > s.M || n_alpha > 80)
+    return fail(ctx, AFQ_EINVAL, "n_alpha must be in [1, min(M, 80)]");
+  if (s.trial_ready) return fail(ctx, AFQ_ESTATE, "trial already set for this system");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int M = s.M, N = (int)n_alpha, G = s.G;
+  std::vector<double> psi((size_t)M * N);
+  if (ptr_is_device) {
+    HIPCHK(hipMemcpyAsync(psi.data(), psi_t, psi.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  } else {
+    std::memcpy(psi.data(), psi_t, psi.size() * 8);
+  }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double d = 0.0;
+      for (int p = 0; p < M; ++p) d += psi[(size_t)p * N + i] * psi[(size_t)p * N + j];
+      if (!(std::fabs(d - (i == j ? 1.0 : 0.0)) <= 1e-10))
+        return fail(ctx, AFQ_EINVAL, "psi_t columns are not orthonormal");
+    }
+  auto& own = ctx->sys_allocs[sys_id];
+  s.N = N;
+  std::vector<double> pt((size_t)N * M);
+  for (int i = 0; i < N; ++i)
+    for (int p = 0; p < M; ++p) pt[(size_t)i * M + p] = psi[(size_t)p * N + i];
+  const size_t MM = (size_t)M * M;
+  TRY(dalloc(ctx, own, &s.psit, (size_t)N * M));
+  TRY(dalloc(ctx, own, &s.Lx, (size_t)(G + 1) * N * M));
+  TRY(dalloc(ctx, own, &s.lbar, (size_t)G));
+  TRY(dalloc(ctx, own, &s.H1, MM));
+  TRY(dalloc(ctx, own, &s.Bhalf, MM));
+  HIPCHK(hipMemcpy(s.psit, pt.data(), pt.size() * 8, hipMemcpyHostToDevice));
+  // Psi_T^T L_g for every g, and Psi_T^T h in the last block
+  GemmArgs g{};
+  g.A = s.psit; g.sAb = 0; g.sAr = M; g.sAk = 1; g.sAkb = 0;
+  g.B = s.L; g.sBb = (int64_t)MM; g.sBc = M; g.sBk = 1; g.sBkb = 0;
+  g.C = s.Lx; g.sCb = (int64_t)N * M; g.sCr = M; g.sCc = 1;
+  g.R = N; g.Cn = M; g.K = M; g.kin = M; g.batch = G; g.alpha = 1.0; g.beta = 0.0;
+  HIPCHK(launch_gemm(g, ctx->stream));
+  g.B = s.h; g.C = s.Lx + (size_t)G * N * M; g.batch = 1;
+  HIPCHK(launch_gemm(g, ctx->stream));
+  HIPCHK(launch_lbar(s, ctx->stream));
+  // H1 = h - 1/2 sum_g L_g L_g + sum_g Lbar_g L_g
+  HIPCHK(hipMemcpyAsync(s.H1, s.h, MM * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  // sum_g L_g L_g in chunks of 32 Cholesky vectors: shorter sequential sums
+  for (int g0 = 0; g0 < G; g0 += 32) {
+    const int gn = G - g0 < 32 ? G - g0 : 32;
+    GemmArgs q{};
+    q.A = s.L + (size_t)g0 * MM; q.sAb = 0; q.sAr = M; q.sAk = 1; q.sAkb = (int64_t)MM;
+    q.B = q.A; q.sBb = 0; q.sBc = M; q.sBk = 1; q.sBkb = (int64_t)MM;
+    q.C = s.H1; q.sCb = 0; q.sCr = M; q.sCc = 1;
+    q.R = M; q.Cn = M; q.K = M * gn; q.kin = M; q.batch = 1; q.alpha = -0.5; q.beta = 1.0;
+    HIPCHK(launch_gemm(q, ctx->stream));
+  }
+  HIPCHK(launch_axpy_L(s, s.lbar, 1.0, s.H1, ctx->stream));
+  std::vector<double> h1(MM), lb(G);
+  HIPCHK(hipMemcpyAsync(h1.data(), s.H1, MM * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(lb.data(), s.lbar, G * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int p = 0; p < M; ++p)  // symmetrise the rounding of the product
+    for (int r = p + 1; r < M; ++r) {
+      const double a = 0.5 * (h1[(size_t)p * M + r] + h1[(size_t)r * M + p]);
+      h1[(size_t)p * M + r] = a;
+      h1[(size_t)r * M + p] = a;
+    }
+  jacobi_eigh(M, h1, s.h1_evals, s.h1_evecs);
+  double l2 = 0.0;
+  for (double v : lb) l2 += v * v;
+  s.e_const = s.e_core - 0.5 * l2;
+  s.tau_b = -1.0;
+  // trial energy E_L(Psi_T): Theta = Psi_T for one walker
+  std::vector<void*> tmp;
+  double *tre, *tim, *lr, *li, *xr, *xi, *el;
+  afq_status r = AFQ_OK;
+  const size_t G1 = (size_t)G + 1;
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &tre, (size_t)N * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &tim, (size_t)N * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &lr, G1);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &li, G1);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &xr, G1);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &xi, G1);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &el, 2);
+  if (r != AFQ_OK) {
+    free_all(tmp);
+    return r;
+  }
+  hipError_t e = hipMemcpyAsync(tre, s.psit, (size_t)N * M * 8, hipMemcpyDeviceToDevice, ctx->stream);
+  std::vector<double> zeros((size_t)N * M, 0.0);
+  if (e == hipSuccess) e = hipMemcpy(tim, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_exchange(s, 1, tre, tim, lr, li, xr, xi, ctx->stream);
+  if (e == hipSuccess) e = launch_energy(s, 1, lr, li, xr, xi, el, nullptr, 0.0, 0.0, ctx->stream);
+  double eh[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(eh, el, 16, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  free_all(tmp);
+  if (e != hipSuccess) return fail(ctx, AFQ_EDEVICE, std::string("trial energy: ") + hipGetErrorString(e));
+  s.e_trial = eh[0];
+  s.trial_ready = true;
+  return AFQ_OK;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, const void* phi0,
+                            int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!s.trial_ready) return fail(ctx, AFQ_ESTATE, "afq_init_trial must precede afq_init_walkers");
+  if (n_walkers < 1 || n_walkers > (1 << 20)) return fail(ctx, AFQ_EINVAL, "n_walkers out of range");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  free_all(s.walker_allocs);
+  s.kmax = 0;
+  s.kb_re = s.kb_im = s.kh = nullptr;
+  auto& own = s.walker_allocs;
+  s.W = (int)n_walkers;
+  const size_t W = s.W, NM = (size_t)s.N * s.M, G1 = (size_t)s.G + 1, MM = (size_t)s.M * s.M;
+  double** planes[] = {&s.phi_re, &s.phi_im, &s.phn_re, &s.phn_im, &s.th_re, &s.th_im, &s.thn_re,
+                       &s.thn_im, &s.t1_re, &s.t1_im, &s.t2_re, &s.t2_im, &s.t3_re, &s.t3_im};
+  for (double** p : planes) TRY(dalloc(ctx, own, p, W * NM));
+  TRY(dalloc(ctx, own, &s.logdet, W * 2));
+  TRY(dalloc(ctx, own, &s.logdet_n, W * 2));
+  TRY(dalloc(ctx, own, &s.weight, W));
+  TRY(dalloc(ctx, own, &s.alive, W));
+  TRY(dalloc(ctx, own, &s.bad, W));
+  TRY(dalloc(ctx, own, &s.qr_logr, W));
+  TRY(dalloc(ctx, own, &s.ell_re, W * G1));
+  TRY(dalloc(ctx, own, &s.ell_im, W * G1));
+  TRY(dalloc(ctx, own, &s.ex_re, W * G1));
+  TRY(dalloc(ctx, own, &s.ex_im, W * G1));
+  TRY(dalloc(ctx, own, &s.eloc, W * 2));
+  TRY(dalloc(ctx, own, &s.ecap, W));
+  TRY(dalloc(ctx, own, &s.x, W * s.G));
+  TRY(dalloc(ctx, own, &s.av_re, W * s.G));
+  TRY(dalloc(ctx, own, &s.av_im, W * s.G));
+  TRY(dalloc(ctx, own, &s.scal, W * 4));
+  TRY(dalloc(ctx, own, &s.ncap, W));
+  TRY(dalloc(ctx, own, &s.A_re, W * MM));
+  TRY(dalloc(ctx, own, &s.A_im, W * MM));
+  TRY(dalloc(ctx, own, &s.kbeta, W * s.N));
+  TRY(dalloc(ctx, own, &s.kdim, W * s.N));
+  TRY(dalloc(ctx, own, &s.est, 2));
+  TRY(dalloc(ctx, own, &s.counters, 4));
+  HIPCHK(hipMemsetAsync(s.counters, 0, 4 * sizeof(int), ctx->stream));
+  if (phi0) {
+    const double* src = (const double*)phi0;
+    std::vector<void*> tmp;
+    double* dtmp = nullptr;
+    if (!ptr_is_device) {
+      TRY(dalloc(ctx, tmp, &dtmp, W * NM * 2));
+      hipError_t e = hipMemcpy(dtmp, phi0, W * NM * 16, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        free_all(tmp);
+        HIPCHK(e);
+      }
+      src = dtmp;
+    }
+    hipError_t e = launch_to_planar(src, s.W, s.M, s.N, s.phi_re, s.phi_im, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    free_all(tmp);
+    HIPCHK(e);
+  } else {
+    hipLaunchKernelGGL(k_fill_trial, dim3((unsigned)((W * NM + 255) / 256)), dim3(256), 0,
+                       ctx->stream, s.W, (int)NM, s.psit, s.phi_re, s.phi_im);
+    HIPCHK(hipGetLastError());
+  }
+  TRY(refresh_green(ctx, s));
+  hipLaunchKernelGGL(k_init_alive, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, ctx->stream,
+                     s.W, s.bad, s.alive, s.weight, 1);
+  HIPCHK(hipGetLastError());
+  TRY(eval_energy(ctx, s, 0.0, 0.0));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return AFQ_OK;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys,
+                               const afq_prop_params* P) try {
+  if (!ctx) return AFQ_EINVAL;
+  if (!sys_ids || !P || n_sys < 1) return fail(ctx, AFQ_EINVAL, "bad arguments");
+  if (!(P->tau > 0.0) || !std::isfinite(P->tau)) return fail(ctx, AFQ_EINVAL, "tau must be > 0");
+  if (P->exp_method != AFQ_EXP_KRYLOV && P->exp_method != AFQ_EXP_TAYLOR)
+    return fail(ctx, AFQ_EINVAL, "unknown exp_method");
+  if (P->exp_order < 1 || P->exp_order > 16) return fail(ctx, AFQ_EINVAL, "exp_order must be in [1, 16]");
+  if (P->precision != AFQ_PREC_FP64) return fail(ctx, AFQ_EINVAL, "precision not available");
+  if (P->n_steps < 0) return fail(ctx, AFQ_EINVAL, "n_steps < 0");
+  if (P->fields && n_sys != 1) return fail(ctx, AFQ_EINVAL, "explicit fields need a single system");
+  HIPCHK(hipSetDevice(ctx->device));
+  std::vector<SysDev*> ss(n_sys);
+  std::vector<double> e0(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    TRY(get_sys(ctx, sys_ids[i], &ss[i]));
+    if (!ss[i]->trial_ready || ss[i]->W == 0)
+      return fail(ctx, AFQ_ESTATE, "system " + std::to_string(sys_ids[i]) + " has no walkers");
+    for (int j = 0; j < i; ++j)
+      if (sys_ids[j] == sys_ids[i]) return fail(ctx, AFQ_EINVAL, "duplicate system id");
+    if (P->exp_method == AFQ_EXP_KRYLOV && ss[i]->M > 512)
+      return fail(ctx, AFQ_EINVAL, "Krylov path supports M <= 512");
+    TRY(ensure_half_step(ctx, *ss[i], P->tau));
+    if (P->exp_method == AFQ_EXP_KRYLOV) TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
+    e0[i] = std::isnan(P->e0) ? ss[i]->e_trial : P->e0;
+    HIPCHK(hipMemsetAsync(ss[i]->counters, 0, 4 * sizeof(int), ctx->stream));
+  }
+  for (int si = 0; si < P->n_steps; ++si)
+    for (int i = 0; i < n_sys; ++i) TRY(step_system(ctx, sys_ids[i], *ss[i], *P, si, i, e0[i]));
+  return AFQ_OK;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, double* eloc_out, double* ell_out,
+                                  int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  if (!eloc_out) return fail(ctx, AFQ_EINVAL, "null eloc_out");
+  HIPCHK(hipSetDevice(ctx->device));
+  TRY(eval_energy(ctx, s, 0.0, 0.0));
+  TRY(copy_out(ctx, eloc_out, s.eloc, (size_t)s.W * 16, ptr_is_device));
+  if (ell_out) {
+    std::vector<void*> tmp;
+    double* d = nullptr;
+    if (!ptr_is_device) TRY(dalloc(ctx, tmp, &d, (size_t)s.W * s.G * 2));
+    double* dst = ptr_is_device ? ell_out : d;
+    hipError_t e = launch_pack_complex(s.ell_re, s.ell_im, s.W, s.G + 1, s.G, dst, ctx->stream);
+    afq_status r = AFQ_OK;
+    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, hipGetErrorString(e));
+    if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, ell_out, d, (size_t)s.W * s.G * 16, 0);
+    free_all(tmp);
+    return r;
+  }
+  return AFQ_OK;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_get_walkers(afq_ctx* ctx, int32_t sys_id, void* phi, double* weight,
+                           double* log_ovlp, int32_t* alive, int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t W = s.W, NM = (size_t)s.N * s.M;
+  if (phi) {
+    std::vector<void*> tmp;
+    double* d = nullptr;
+    if (!ptr_is_device) TRY(dalloc(ctx, tmp, &d, W * NM * 2));
+    double* dst = ptr_is_device ? (double*)phi : d;
+    hipError_t e = launch_from_planar(s.phi_re, s.phi_im, s.W, s.M, s.N, dst, ctx->stream);
+    afq_status r = AFQ_OK;
+    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, hipGetErrorString(e));
+    if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, phi, d, W * NM * 16, 0);
+    free_all(tmp);
+    TRY(r);
+  }
+  if (weight) TRY(copy_out(ctx, weight, s.weight, W * 8, ptr_is_device));
+  if (log_ovlp) TRY(copy_out(ctx, log_ovlp, s.logdet, W * 16, ptr_is_device));
+  if (alive) TRY(copy_out(ctx, alive, s.alive, W * 4, ptr_is_device));
+  return AFQ_OK;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_set_walkers(afq_ctx* ctx, int32_t sys_id, const void* phi, const double* weight,
+                           int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t W = s.W, NM = (size_t)s.N * s.M;
+  if (phi) {
+    std::vector<void*> tmp;
+    const double* src = (const double*)phi;
+    if (!ptr_is_device) {
+      double* d = nullptr;
+      TRY(dalloc(ctx, tmp, &d, W * NM * 2));
+      hipError_t e = hipMemcpy(d, phi, W * NM * 16, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        free_all(tmp);
+        HIPCHK(e);
+      }
+      src = d;
+    }
+    hipError_t e = launch_to_planar(src, s.W, s.M, s.N, s.phi_re, s.phi_im, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    free_all(tmp);
+    HIPCHK(e);
+  }
+  if (weight) TRY(copy_in(ctx, s.weight, weight, W, ptr_is_device));
+  TRY(refresh_green(ctx, s));
+  hipLaunchKernelGGL(k_init_alive, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, ctx->stream,
+                     s.W, s.bad, s.alive, s.weight, 0);
+  HIPCHK(hipGetLastError());
+  TRY(eval_energy(ctx, s, 0.0, 0.0));
+  return AFQ_OK;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_fill_fields(afq_ctx* ctx, uint64_t seed, uint64_t sys_id, uint64_t step,
+                           int64_t n_walkers, int64_t n_chol, double* out_dev) {
+  if (!ctx) return AFQ_EINVAL;
+  if (!out_dev || n_walkers < 1 || n_chol < 1) return fail(ctx, AFQ_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(launch_fields(seed, sys_id, step, (int)n_walkers, (int)n_chol, out_dev, ctx->stream));
+  return AFQ_OK;
+}
+
+afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4) {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  if (!out4) return fail(ctx, AFQ_EINVAL, "null out4");
+  if (!sp->W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  HIPCHK(hipSetDevice(ctx->device));
+  int h[4];
+  HIPCHK(hipMemcpyAsync(h, sp->counters, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < 4; ++i) out4[i] = h[i];
+  return AFQ_OK;
+}
+
+afq_status afq_local_energy_adjoint(afq_ctx* ctx, int32_t sys_id, const double* dE_dEL,
+                                    double* grad_h, double* grad_L, int ptr_is_device) {
+  (void)sys_id; (void)dE_dEL; (void)grad_h; (void)grad_L; (void)ptr_is_device;
+  return fail(ctx, AFQ_ESTATE, "adjoint not available in this build");
+}
+
+afq_status afq_force_bias_adjoint(afq_ctx* ctx, int32_t sys_id, const double* d_ell,
+                                  double* grad_L, int ptr_is_device) {
+  (void)sys_id; (void)d_ell; (void)grad_L; (void)ptr_is_device;
+  return fail(ctx, AFQ_ESTATE, "adjoint not available in this build");
+}
+
+afq_status afq_profile(afq_ctx* ctx, int enable) {
+  if (!ctx) return AFQ_EINVAL;
+  ctx->profiling = enable != 0;
+  return AFQ_OK;
+}
+
+afq_status afq_profile_read(afq_ctx* ctx, double* ms_out, int64_t* launches_out, int n) {
+  if (!ctx) return AFQ_EINVAL;
+  if (n < 0 || n > AFQ_PH_COUNT) return fail(ctx, AFQ_EINVAL, "n out of range");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (const PhaseEv& e : ctx->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      ctx->ph_ms[e.phase] += ms;
+      ctx->ph_n[e.phase] += 1;
+    }
+    ctx->ev_pool.push_back(e.a);
+    ctx->ev_pool.push_back(e.b);
+  }
+  ctx->pending.clear();
+  for (int i = 0; i < n; ++i) {
+    if (ms_out) ms_out[i] = ctx->ph_ms[i];
+    if (launches_out) launches_out[i] = ctx->ph_n[i];
+  }
+  for (int i = 0; i < AFQ_PH_COUNT; ++i) {
+    ctx->ph_ms[i] = 0.0;
+    ctx->ph_n[i] = 0;
+  }
+  return AFQ_OK;
+}
+
+afq_status afq_sync(afq_ctx* ctx) {
+  if (!ctx) return AFQ_EINVAL;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return AFQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,562 @@
+// Dense contractions of the walker step on the FP64 matrix cores:
+//  * generic strided GEMM (set-up work: Psi_T^T L_g, sum_g L_g L_g, ...),
+//  * the exact one-body half-step Phi <- exp(-tau H1/2) Phi (Sec. III.B),
+//  * the operator build A^w = i sqrt(tau) sum_g (x_g - fbar_g) L_g (Eq. heffTOT),
+//  * the operator-orbital product A^w psi that every exponential method
+//    repeats k times (Sec. IV), with the Taylor and Krylov drivers.
+#include "afq_device.h"
+#include "afq_internal.h"
+
+namespace {
+
+// Map a linear block id to (outer, inner) so that the inner_n blocks that
+// share an outer index are dispatched to the same XCD (block ids are handed
+// to the 8 XCDs round-robin) and share its L2.  Grid = ceil(outer_n/8)*8*inner_n.
+AFQ_DEV bool xcd_swizzle(int id, int inner_n, int outer_n, int& outer, int& inner) {
+  const int xcd = id & 7, slot = id >> 3;
+  const int grp = slot / inner_n;
+  inner = slot - grp * inner_n;
+  outer = grp * 8 + xcd;
+  return outer < outer_n;
+}
+inline int xcd_grid(int outer_n, int inner_n) { return ((outer_n + 7) / 8) * 8 * inner_n; }
+
+// ------------------------------------------------------------ generic GEMM
+
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_gemm_generic(GemmArgs g) {
+  constexpr int ROWS = 32 * MT, COLS = 32 * NT;
+  __shared__ double As[ROWS * kLDK];
+  __shared__ double Bs[COLS * kLDK];
+  const int nct = (g.Cn + COLS - 1) / COLS;
+  const int rt = blockIdx.x / nct, ct = blockIdx.x % nct;
+  const int64_t b = blockIdx.y;
+  const int r0 = rt * ROWS, c0 = ct * COLS;
+  const int nr = min(ROWS, g.R - r0), nc = min(COLS, g.Cn - c0);
+  const WaveSplit ws = wave_split<MT, NT>(nr, nc);
+  TileAcc<MT, NT> acc;
+  acc.zero();
+  const double* A = g.A + b * g.sAb;
+  const double* B = g.B + b * g.sBb;
+  auto getA = [&](int r, int k) {
+    return A[(int64_t)(r0 + r) * g.sAr + (int64_t)(k / g.kin) * g.sAkb + (int64_t)(k % g.kin) * g.sAk];
+  };
+  auto getB = [&](int c, int k) {
+    return B[(int64_t)(c0 + c) * g.sBc + (int64_t)(k / g.kin) * g.sBkb + (int64_t)(k % g.kin) * g.sBk];
+  };
+  auto fa = [&](int k0, double* S) {
+    if (g.sAk == 1) stage_rows<ROWS>(S, k0, g.K, nr, getA);
+    else stage_rows_kmajor<ROWS>(S, k0, g.K, nr, getA);
+  };
+  auto fb = [&](int k0, double* S) {
+    if (g.sBk == 1) stage_rows<COLS>(S, k0, g.K, nc, getB);
+    else stage_rows_kmajor<COLS>(S, k0, g.K, nc, getB);
+  };
+  tile_gemm<MT, NT>(g.K, ws, fa, fb, As, Bs, acc);
+  double* C = g.C + b * g.sCb;
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      if (i >= ws.mtv || j >= ws.ntv) continue;
+      const int c = acc_col(ws, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = acc_row(ws, i, e);
+        if (r < nr && c < nc) {
+          const int64_t idx = (int64_t)(r0 + r) * g.sCr + (int64_t)(c0 + c) * g.sCc;
+          double v = g.alpha * acc.c[i][j][e];
+          if (g.beta != 0.0) v += g.beta * C[idx];
+          C[idx] = v;
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------ one-body step
+// out[(plane, w, j)][p] = sum_q in[(plane, w, j)][q] B[p][q]   (B symmetric)
+
+constexpr int OB_MT = 4, OB_NT = 5;
+
+__global__ __launch_bounds__(256) void k_onebody(int WN, int M, const double* __restrict__ in_re,
+                                                 const double* __restrict__ in_im,
+                                                 const double* __restrict__ Bm,
+                                                 double* __restrict__ out_re,
+                                                 double* __restrict__ out_im) {
+  constexpr int ROWS = 32 * OB_MT, COLS = 32 * OB_NT;
+  __shared__ double As[ROWS * kLDK];
+  __shared__ double Bs[COLS * kLDK];
+  const int nct = (M + COLS - 1) / COLS;
+  const int rt = blockIdx.x / nct, ct = blockIdx.x % nct;
+  const int r0 = rt * ROWS, c0 = ct * COLS;
+  const int R = 2 * WN;
+  const int nr = min(ROWS, R - r0), nc = min(COLS, M - c0);
+  const WaveSplit ws = wave_split<OB_MT, OB_NT>(nr, nc);
+  TileAcc<OB_MT, OB_NT> acc;
+  acc.zero();
+  auto getA = [&](int r, int k) {
+    const int64_t rr = r0 + r;
+    return rr < WN ? in_re[rr * M + k] : in_im[(rr - WN) * M + k];
+  };
+  auto getB = [&](int c, int k) { return Bm[(int64_t)(c0 + c) * M + k]; };
+  auto fa = [&](int k0, double* S) { stage_rows<ROWS>(S, k0, M, nr, getA); };
+  auto fb = [&](int k0, double* S) { stage_rows<COLS>(S, k0, M, nc, getB); };
+  tile_gemm<OB_MT, OB_NT>(M, ws, fa, fb, As, Bs, acc);
+#pragma unroll
+  for (int i = 0; i < OB_MT; ++i)
+#pragma unroll
+    for (int j = 0; j < OB_NT; ++j) {
+      if (i >= ws.mtv || j >= ws.ntv) continue;
+      const int c = acc_col(ws, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = acc_row(ws, i, e);
+        if (r < nr && c < nc) {
+          const int64_t rr = r0 + r;
+          if (rr < WN) out_re[rr * M + c0 + c] = acc.c[i][j][e];
+          else out_im[(rr - WN) * M + c0 + c] = acc.c[i][j][e];
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------ operator build
+// A_plane[w][pq] = sum_g a_plane[w][g] L[g][pq],  a = i sqrt(tau) (x - fbar)
+
+constexpr int OP_MT = 4, OP_NT = 5;
+
+__global__ __launch_bounds__(256) void k_opbuild(int W, int G, int64_t MM,
+                                                 const double* __restrict__ a_re,
+                                                 const double* __restrict__ a_im,
+                                                 const double* __restrict__ L,
+                                                 double* __restrict__ A_re,
+                                                 double* __restrict__ A_im, int n_rt, int n_ct) {
+  constexpr int ROWS = 32 * OP_MT, COLS = 32 * OP_NT;
+  __shared__ double As[ROWS * kLDK];
+  __shared__ double Bs[COLS * kLDK];
+  int ct, rt;
+  if (!xcd_swizzle(blockIdx.x, n_rt, n_ct, ct, rt)) return;
+  const int r0 = rt * ROWS;
+  const int64_t c0 = (int64_t)ct * COLS;
+  const int R = 2 * W;
+  const int nr = min(ROWS, R - r0);
+  const int nc = (int)min((int64_t)COLS, MM - c0);
+  const WaveSplit ws = wave_split<OP_MT, OP_NT>(nr, nc);
+  TileAcc<OP_MT, OP_NT> acc;
+  acc.zero();
+  auto getA = [&](int r, int k) {
+    const int rr = r0 + r;
+    return rr < W ? a_re[(int64_t)rr * G + k] : a_im[(int64_t)(rr - W) * G + k];
+  };
+  auto getB = [&](int c, int k) { return L[(int64_t)k * MM + c0 + c]; };
+  auto fa = [&](int k0, double* S) { stage_rows<ROWS>(S, k0, G, nr, getA); };
+  auto fb = [&](int k0, double* S) { stage_rows_kmajor<COLS>(S, k0, G, nc, getB); };
+  tile_gemm<OP_MT, OP_NT>(G, ws, fa, fb, As, Bs, acc);
+#pragma unroll
+  for (int i = 0; i < OP_MT; ++i)
+#pragma unroll
+    for (int j = 0; j < OP_NT; ++j) {
+      if (i >= ws.mtv || j >= ws.ntv) continue;
+      const int c = acc_col(ws, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = acc_row(ws, i, e);
+        if (r < nr && c < nc) {
+          const int rr = r0 + r;
+          if (rr < W) A_re[(int64_t)rr * MM + c0 + c] = acc.c[i][j][e];
+          else A_im[(int64_t)(rr - W) * MM + c0 + c] = acc.c[i][j][e];
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------ A^w psi
+// For walker w and orbitals j < N: out[j][p] = sum_q A^w[p][q] v[j][q]
+// (complex).  Real form: rows r = (plane, j), K = (q, plane') of length 2M:
+//   row (re, j): [ v_re[j][q],  -v_im[j][q] ],   row (im, j): [ v_im, v_re ]
+//   col p:       [ A_re[p][q],   A_im[p][q] ]
+// mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
+
+constexpr int MV_MT = 5, MV_NT = 4;
+
+struct VecRef {
+  const double* re;
+  const double* im;
+  int64_t sw, sj;  // walker / orbital strides (elements)
+};
+struct VecOut {
+  double* re;
+  double* im;
+  int64_t sw, sj;
+};
+
+__global__ __launch_bounds__(256) void k_matvec(int W, int N, int M, VecRef v,
+                                                const double* __restrict__ A_re,
+                                                const double* __restrict__ A_im, VecOut o,
+                                                int mode, double inv_n, VecOut sum, int n_ct) {
+  constexpr int ROWS = 32 * MV_MT, COLS = 32 * MV_NT;
+  __shared__ double As[ROWS * kLDK];
+  __shared__ double Bs[COLS * kLDK];
+  int w, ct;
+  if (!xcd_swizzle(blockIdx.x, n_ct, W, w, ct)) return;
+  // balanced column blocks: n_ct blocks over ceil(M/16) tiles
+  const int TC = (M + 15) / 16;
+  const int tpb = (TC + n_ct - 1) / n_ct;
+  const int c0 = ct * tpb * 16;
+  if (c0 >= M) return;
+  const int nc = min(tpb * 16, M - c0);
+  const int nr = 2 * N;
+  const WaveSplit ws = wave_split<MV_MT, MV_NT>(nr, nc);
+  TileAcc<MV_MT, MV_NT> acc;
+  acc.zero();
+  const double* vre = v.re + (int64_t)w * v.sw;
+  const double* vim = v.im + (int64_t)w * v.sw;
+  const int64_t MM = (int64_t)M * M;
+  const double* Are = A_re + (int64_t)w * MM;
+  const double* Aim = A_im + (int64_t)w * MM;
+  auto getA = [&](int r, int k) {
+    const bool im_row = r >= N;
+    const int j = im_row ? r - N : r;
+    if (k < M) return im_row ? vim[j * v.sj + k] : vre[j * v.sj + k];
+    const int q = k - M;
+    return im_row ? vre[j * v.sj + q] : -vim[j * v.sj + q];
+  };
+  auto getB = [&](int c, int k) {
+    const int64_t p = c0 + c;
+    return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
+  };
+  auto fa = [&](int k0, double* S) { stage_rows<ROWS>(S, k0, 2 * M, nr, getA); };
+  auto fb = [&](int k0, double* S) { stage_rows<COLS>(S, k0, 2 * M, nc, getB); };
+  tile_gemm<MV_MT, MV_NT>(2 * M, ws, fa, fb, As, Bs, acc);
+#pragma unroll
+  for (int i = 0; i < MV_MT; ++i)
+#pragma unroll
+    for (int jt = 0; jt < MV_NT; ++jt) {
+      if (i >= ws.mtv || jt >= ws.ntv) continue;
+      const int c = acc_col(ws, jt);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = acc_row(ws, i, e);
+        if (r < nr && c < nc) {
+          const bool im_row = r >= N;
+          const int j = im_row ? r - N : r;
+          const int64_t off = (int64_t)w * o.sw + (int64_t)j * o.sj + c0 + c;
+          double val = acc.c[i][jt][e];
+          if (mode == 1) {
+            val *= inv_n;
+            const int64_t soff = (int64_t)w * sum.sw + (int64_t)j * sum.sj + c0 + c;
+            if (im_row) sum.im[soff] += val;
+            else sum.re[soff] += val;
+          }
+          if (im_row) o.im[off] = val;
+          else o.re[off] = val;
+        }
+      }
+    }
+}
+
+int matvec_col_blocks(int M) {
+  const int TC = (M + 15) / 16;
+  const int per = 2 * MV_NT;
+  return (TC + per - 1) / per;
+}
+
+hipError_t run_matvec(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+                      hipStream_t st) {
+  if (2 * s.N > 32 * MV_MT) return hipErrorInvalidValue;
+  const int n_ct = matvec_col_blocks(s.M);
+  hipLaunchKernelGGL(k_matvec, dim3(xcd_grid(s.W, n_ct)), dim3(256), 0, st, s.W, s.N, s.M, v,
+                     s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ Krylov pieces
+// One 64-lane wave per (walker, orbital).  M <= 64 * KV_R.
+
+constexpr int KV_R = 8;
+
+// b_0 = psi / ||psi||, beta = ||psi||, dim = k (0 if psi == 0).
+__global__ __launch_bounds__(256) void k_krylov_init(int WN, int M, int kmax, int k,
+                                                     const double* __restrict__ in_re,
+                                                     const double* __restrict__ in_im,
+                                                     double* __restrict__ kb_re,
+                                                     double* __restrict__ kb_im,
+                                                     double* __restrict__ kbeta,
+                                                     int* __restrict__ kdim) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (o >= WN) return;
+  const double* xr = in_re + (int64_t)o * M;
+  const double* xi = in_im + (int64_t)o * M;
+  double s = 0.0;
+  for (int p = lane; p < M; p += 64) s += xr[p] * xr[p] + xi[p] * xi[p];
+  s = wave_sum(s);
+  const double beta = sqrt(s);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  double* br = kb_re + (int64_t)o * kmax * M;
+  double* bi = kb_im + (int64_t)o * kmax * M;
+  for (int p = lane; p < M; p += 64) {
+    br[p] = xr[p] * inv;
+    bi[p] = xi[p] * inv;
+  }
+  if (lane == 0) {
+    kbeta[o] = beta;
+    kdim[o] = beta > 0.0 ? k : 0;
+  }
+}
+
+// Arnoldi step m: w = A b_m (in wv) is orthogonalised against b_0..b_m by two
+// passes of modified Gram-Schmidt; H[0..m][m] accumulates the projections,
+// H[m+1][m] = ||w|| and b_{m+1} = w / ||w|| unless the residual vanishes
+// against ||A b_m|| (happy breakdown: dim = m + 1, b_{m+1} = 0).
+__global__ __launch_bounds__(256) void k_krylov_orth(int WN, int M, int kmax, int k, int m,
+                                                     const double* __restrict__ wv_re,
+                                                     const double* __restrict__ wv_im,
+                                                     double* __restrict__ kb_re,
+                                                     double* __restrict__ kb_im,
+                                                     double* __restrict__ kh,
+                                                     int* __restrict__ kdim,
+                                                     double breakdown_rel) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (o >= WN) return;
+  if (m >= kdim[o]) return;
+  double wr[KV_R], wi[KV_R];
+  const double* xr = wv_re + (int64_t)o * M;
+  const double* xi = wv_im + (int64_t)o * M;
+#pragma unroll
+  for (int t = 0; t < KV_R; ++t) {
+    const int p = lane + 64 * t;
+    wr[t] = p < M ? xr[p] : 0.0;
+    wi[t] = p < M ? xi[p] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < KV_R; ++t) s += wr[t] * wr[t] + wi[t] * wi[t];
+  const double wnorm = sqrt(wave_sum(s));
+  double* br = kb_re + (int64_t)o * kmax * M;
+  double* bi = kb_im + (int64_t)o * kmax * M;
+  double* H = kh + (int64_t)o * kmax * kmax * 2;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i <= m; ++i) {
+      double ar = 0.0, ai = 0.0;
+#pragma unroll
+      for (int t = 0; t < KV_R; ++t) {
+        const int p = lane + 64 * t;
+        if (p < M) {
+          const double b_r = br[i * M + p], b_i = bi[i * M + p];
+          ar += b_r * wr[t] + b_i * wi[t];
+          ai += b_r * wi[t] - b_i * wr[t];
+        }
+      }
+      const double cr = wave_sum(ar), ci = wave_sum(ai);
+#pragma unroll
+      for (int t = 0; t < KV_R; ++t) {
+        const int p = lane + 64 * t;
+        if (p < M) {
+          const double b_r = br[i * M + p], b_i = bi[i * M + p];
+          wr[t] -= cr * b_r - ci * b_i;
+          wi[t] -= cr * b_i + ci * b_r;
+        }
+      }
+      if (lane == 0) {
+        double* h = H + (i * kmax + m) * 2;
+        if (pass == 0) {
+          h[0] = cr;
+          h[1] = ci;
+        } else {
+          h[0] += cr;
+          h[1] += ci;
+        }
+      }
+    }
+  }
+  if (m + 1 >= k) return;
+  s = 0.0;
+#pragma unroll
+  for (int t = 0; t < KV_R; ++t) s += wr[t] * wr[t] + wi[t] * wi[t];
+  const double hn = sqrt(wave_sum(s));
+  const bool brk = !(hn > breakdown_rel * wnorm) || hn == 0.0;
+  const double inv = brk ? 0.0 : 1.0 / hn;
+#pragma unroll
+  for (int t = 0; t < KV_R; ++t) {
+    const int p = lane + 64 * t;
+    if (p < M) {
+      br[(m + 1) * M + p] = wr[t] * inv;
+      bi[(m + 1) * M + p] = wi[t] * inv;
+    }
+  }
+  if (lane == 0) {
+    H[((m + 1) * kmax + m) * 2 + 0] = brk ? 0.0 : hn;
+    H[((m + 1) * kmax + m) * 2 + 1] = 0.0;
+    if (brk) kdim[o] = m + 1;
+  }
+}
+
+// out = beta * B_d exp(H_d) e_1 with d = dim <= 16.  exp(H_d) e_1 by s
+// Taylor substeps of 18 terms each, s = ceil(||H_d||_1 / 0.5), so that every
+// substep has a norm of at most 1/2.  Lane i < d owns row i of H_d and
+// component i of the vector; the vector is exchanged by lane shuffles.
+__global__ __launch_bounds__(256) void k_krylov_combine(int WN, int M, int kmax, int k,
+                                                        const double* __restrict__ kb_re,
+                                                        const double* __restrict__ kb_im,
+                                                        const double* __restrict__ kh,
+                                                        const double* __restrict__ kbeta,
+                                                        const int* __restrict__ kdim,
+                                                        double* __restrict__ out_re,
+                                                        double* __restrict__ out_im,
+                                                        int* __restrict__ nbreak) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (o >= WN) return;
+  const int d = kdim[o];
+  const double beta = kbeta[o];
+  const double* H = kh + (int64_t)o * kmax * kmax * 2;
+  double hr[16], hi[16];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    // upper Hessenberg: only entries on or above the subdiagonal exist
+    const bool v = lane < d && l < d && lane <= l + 1;
+    hr[l] = v ? H[(lane * kmax + l) * 2 + 0] : 0.0;
+    hi[l] = v ? H[(lane * kmax + l) * 2 + 1] : 0.0;
+  }
+  // 1-norm: max over columns l of sum_i |H[i][l]| (column sums via shuffles)
+  double nrm = 0.0;
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    const double c = wave_sum(sqrt(hr[l] * hr[l] + hi[l] * hi[l]));
+    nrm = fmax(nrm, c);
+  }
+  int nsub = (int)ceil(nrm / 0.5);
+  if (nsub < 1) nsub = 1;
+  const double sc = 1.0 / nsub;
+  double yr = (lane == 0) ? 1.0 : 0.0, yi = 0.0;
+  for (int sub = 0; sub < nsub; ++sub) {
+    double tr = yr, ti = yi;
+    double acr = yr, aci = yi;
+    for (int n = 1; n <= 18; ++n) {
+      double nr = 0.0, ni = 0.0;
+#pragma unroll
+      for (int l = 0; l < 16; ++l) {
+        const double u = __shfl(tr, l, 64), v = __shfl(ti, l, 64);
+        nr += hr[l] * u - hi[l] * v;
+        ni += hr[l] * v + hi[l] * u;
+      }
+      const double f = sc / n;
+      tr = nr * f;
+      ti = ni * f;
+      acr += tr;
+      aci += ti;
+    }
+    yr = lane < d ? acr : 0.0;
+    yi = lane < d ? aci : 0.0;
+  }
+  double ur[16], ui[16];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    ur[l] = __shfl(yr, l, 64) * beta;
+    ui[l] = __shfl(yi, l, 64) * beta;
+  }
+  const double* br = kb_re + (int64_t)o * kmax * M;
+  const double* bi = kb_im + (int64_t)o * kmax * M;
+  double* xr = out_re + (int64_t)o * M;
+  double* xi = out_im + (int64_t)o * M;
+  for (int p = lane; p < M; p += 64) {
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm) {
+      if (mm < d) {
+        const double b_r = br[mm * M + p], b_i = bi[mm * M + p];
+        ar += ur[mm] * b_r - ui[mm] * b_i;
+        ai += ur[mm] * b_i + ui[mm] * b_r;
+      }
+    }
+    xr[p] = ar;
+    xi[p] = ai;
+  }
+  if (lane == 0 && d < k && d > 0 && nbreak) atomicAdd(nbreak, 1);
+}
+
+}  // namespace
+
+// ==================================================================== launchers
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
+  constexpr int MT = 2, NT = 2;
+  const int nrt = (g.R + 32 * MT - 1) / (32 * MT);
+  const int nct = (g.Cn + 32 * NT - 1) / (32 * NT);
+  hipLaunchKernelGGL((k_gemm_generic<MT, NT>), dim3(nrt * nct, g.batch), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
+                          double* out_im, hipStream_t st) {
+  const int WN = s.W * s.N;
+  const int nrt = (2 * WN + 32 * OB_MT - 1) / (32 * OB_MT);
+  const int nct = (s.M + 32 * OB_NT - 1) / (32 * OB_NT);
+  hipLaunchKernelGGL(k_onebody, dim3(nrt * nct), dim3(256), 0, st, WN, s.M, in_re, in_im,
+                     s.Bhalf, out_re, out_im);
+  return hipGetLastError();
+}
+
+hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
+  const int64_t MM = (int64_t)s.M * s.M;
+  const int n_rt = (2 * s.W + 32 * OP_MT - 1) / (32 * OP_MT);
+  const int n_ct = (int)((MM + 32 * OP_NT - 1) / (32 * OP_NT));
+  hipLaunchKernelGGL(k_opbuild, dim3(xcd_grid(n_ct, n_rt)), dim3(256), 0, st, s.W, s.G, MM,
+                     s.av_re, s.av_im, s.L, s.A_re, s.A_im, n_rt, n_ct);
+  return hipGetLastError();
+}
+
+hipError_t launch_taylor(SysDev& s, int k, const double* in_re, const double* in_im,
+                         double* out_re, double* out_im, double* s1_re, double* s1_im,
+                         double* s2_re, double* s2_im, hipStream_t st) {
+  const size_t bytes = sizeof(double) * (size_t)s.W * s.N * s.M;
+  hipError_t e = hipMemcpyAsync(out_re, in_re, bytes, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(out_im, in_im, bytes, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  const int64_t sw = (int64_t)s.N * s.M, sj = s.M;
+  const double* cur_re = in_re;
+  const double* cur_im = in_im;
+  double* bufs_re[2] = {s1_re, s2_re};
+  double* bufs_im[2] = {s1_im, s2_im};
+  for (int n = 1; n <= k; ++n) {
+    VecRef v{cur_re, cur_im, sw, sj};
+    VecOut o{bufs_re[n & 1], bufs_im[n & 1], sw, sj};
+    VecOut sum{out_re, out_im, sw, sj};
+    e = run_matvec(s, v, o, 1, 1.0 / n, sum, st);
+    if (e != hipSuccess) return e;
+    cur_re = bufs_re[n & 1];
+    cur_im = bufs_im[n & 1];
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_krylov(SysDev& s, int k, const double* in_re, const double* in_im,
+                         double* out_re, double* out_im, double* wv_re, double* wv_im,
+                         hipStream_t st) {
+  if (k > s.kmax || k > 16 || s.M > 64 * KV_R) return hipErrorInvalidValue;
+  const int WN = s.W * s.N;
+  const int nb = (WN + 3) / 4;
+  hipLaunchKernelGGL(k_krylov_init, dim3(nb), dim3(256), 0, st, WN, s.M, s.kmax, k, in_re, in_im,
+                     s.kb_re, s.kb_im, s.kbeta, s.kdim);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t sw = (int64_t)s.N * s.M;
+  for (int m = 0; m < k; ++m) {
+    VecRef v{s.kb_re + (int64_t)m * s.M, s.kb_im + (int64_t)m * s.M, (int64_t)s.N * s.kmax * s.M,
+             (int64_t)s.kmax * s.M};
+    VecOut o{wv_re, wv_im, sw, s.M};
+    e = run_matvec(s, v, o, 0, 1.0, o, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_krylov_orth, dim3(nb), dim3(256), 0, st, WN, s.M, s.kmax, k, m, wv_re,
+                       wv_im, s.kb_re, s.kb_im, s.kh, s.kdim, 1e-12);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_krylov_combine, dim3(nb), dim3(256), 0, st, WN, s.M, s.kmax, k, s.kb_re,
+                     s.kb_im, s.kh, s.kbeta, s.kdim, out_re, out_im,
+                     s.counters ? s.counters + 2 : nullptr);
+  return hipGetLastError();
+}

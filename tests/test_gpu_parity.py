@@ -1,0 +1,292 @@
+"""GPU parity: the HIP walker step against the FP64 oracle, element by
+element, on the same seeded inputs and fields.  All calls go through the
+C ABI (ctypes binding)."""
+import numpy as np
+import pytest
+
+import afq_workloads as W
+import gpu_common as C
+from oracle import afq_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    C.require_gpu()
+    from paper_2403_02542_amd import afq
+    c = afq.Context(0)
+    yield c
+    c.close()
+
+
+def test_fields_match_generator(ctx):
+    """Library Philox4x64-10 + Box-Muller == the input generator."""
+    import torch
+    for (seed, sid, step, nw, ng) in [(0, 0, 0, 16, 96), (7, 3, 11, 5, 10), (0, 1, 2, 3, 1)]:
+        out = torch.empty((nw, ng), dtype=torch.float64, device="cuda")
+        ctx.fill_fields(seed, sid, step, out)
+        ref = W.fields(seed, sid, step, nw, ng)
+        assert np.abs(out.cpu().numpy() - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_trial_energy_and_coulomb_vector(ctx, cfg):
+    case = C.Case.from_config(cfg)
+    sid = case.gpu(ctx, 3)
+    p = case.oracle(0.05)
+    el, ell = ctx.local_energy_batch(sid, ell_out=True)
+    assert np.abs(el - p.e0).max() < C.RTOL * abs(p.e0)
+    assert np.abs(ell - p.lbar[None, :]).max() < C.RTOL * max(1.0, np.abs(p.lbar).max())
+
+
+@pytest.mark.parametrize("shape", [(24, 5, 96), (37, 7, 50), (70, 11, 33), (16, 1, 1), (130, 40, 17)])
+def test_local_energy_random_walkers(ctx, shape):
+    """E_L and ell for random complex walkers; shapes with ragged tails in
+    every tiled dimension (M, N, G not multiples of the tile sizes)."""
+    M, N, G = shape
+    case = C.Case.random(M, N, G, seed=M + N + G, sigma_A=0.3 / np.sqrt(M))
+    rng = np.random.default_rng(1)
+    nw = 13
+    phi = case.psi[None] + 0.3 * (rng.normal(size=(nw, M, N)) + 1j * rng.normal(size=(nw, M, N)))
+    sid = case.gpu(ctx, nw, phi)
+    p = case.oracle(0.05)
+    el, ell = ctx.local_energy_batch(sid, ell_out=True)
+    st = ctx.get_walkers(sid)
+    for w in range(nw):
+        ld, th = O.overlap(case.psi, phi[w])
+        e = O.local_energy(p, phi[w], th)
+        assert abs(el[w] - e) < C.RTOL * max(1.0, abs(e)), (w, el[w], e)
+        l = O.coulomb_vector(p, th)
+        assert C.rel(ell[w], l) < C.RTOL
+        assert abs(st["log_ovlp"][w].real - ld.real) < C.RTOL * max(1.0, abs(ld.real))
+        assert abs(C.wrap(st["log_ovlp"][w].imag - ld.imag)) < C.RTOL
+    assert np.abs(st["phi"] - phi).max() == 0.0
+
+
+@pytest.mark.parametrize("method", [O.EXP_KRYLOV, O.EXP_TAYLOR])
+def test_propagation_c1_all_walkers(ctx, method):
+    """Config c1 in full: 16 walkers x 20 steps, Krylov k=6 / Taylor k=6."""
+    cfg = W.CONFIGS["c1"]
+    case = C.Case.from_config("c1")
+    worst, flagged, sid = C.run_pair(case, ctx, tau=cfg.tau, k=cfg.k, method=method,
+                                     reorth=cfg.reorth_every, n_steps=cfg.steps,
+                                     n_walkers=cfg.W, track=list(range(cfg.W)))
+    print("c1", method, worst, "flagged", sorted(flagged))
+    assert len(flagged) <= 2
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+def test_propagation_c2_subset(ctx):
+    """Config c2 (256 walkers on the GPU), 6 walkers tracked by the oracle
+    over 50 steps (walkers are independent given their fields)."""
+    cfg = W.CONFIGS["c2"]
+    case = C.Case.from_config("c2")
+    worst, flagged, sid = C.run_pair(case, ctx, tau=cfg.tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                     reorth=cfg.reorth_every, n_steps=cfg.steps,
+                                     n_walkers=cfg.W, track=[0, 77, 200, 255])
+    print("c2", worst, "flagged", sorted(flagged))
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+def test_propagation_c3_subset(ctx):
+    """Production shape c3 (512 walkers on the GPU, QR every 5 steps), 3
+    walkers tracked by the oracle over 10 steps."""
+    cfg = W.CONFIGS["c3"]
+    case = C.Case.from_config("c3")
+    worst, flagged, sid = C.run_pair(case, ctx, tau=cfg.tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                     reorth=cfg.reorth_every, n_steps=10,
+                                     n_walkers=cfg.W, track=[0, 300, 511])
+    print("c3", worst, "flagged", sorted(flagged))
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+def test_single_step_parity_c3(ctx):
+    """Production shape, oracle restarted from the GPU state every step:
+    the error of one step (including the QR step) is far below 1e-10."""
+    cfg = W.CONFIGS["c3"]
+    case = C.Case.from_config("c3")
+    worst, flagged, sid = C.run_pair(case, ctx, tau=cfg.tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                     reorth=cfg.reorth_every, n_steps=6,
+                                     n_walkers=cfg.W, track=[1, 300], resync=True)
+    print("c3 single step", worst, "flagged", sorted(flagged))
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+def test_propagation_reorth_schedule_and_large_tau(ctx):
+    """QR every 3 steps, tau = 0.1, ragged shape; Krylov is not invariant
+    under Phi -> Phi R, so this checks the schedule and the QR convention."""
+    case = C.Case.random(45, 9, 70, seed=5, sigma_A=0.2 / np.sqrt(45))
+    worst, flagged, sid = C.run_pair(case, ctx, tau=0.1, k=7, method=O.EXP_KRYLOV, reorth=3,
+                                     n_steps=12, n_walkers=10, track=list(range(10)))
+    print("reorth3", worst, "flagged", sorted(flagged))
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+def test_batch_independence_bitwise(ctx):
+    """A batch of 12 walkers equals a batch of its first 5, bitwise, for the
+    same fields (walkers do not interact)."""
+    import torch
+    case = C.Case.from_config("c1")
+    from paper_2403_02542_amd import afq
+    res = []
+    for nw in (12, 5):
+        c2 = afq.Context(0)
+        sid = case.gpu(c2, nw)
+        for s in range(4):
+            x = C.to_dev(W.fields(0, 0, s, 12, case.G)[:nw])
+            c2.propagate_batch(sid, tau=0.01, n_steps=1, exp_order=6, step0=s, fields=x)
+        torch.cuda.synchronize()
+        res.append(c2.get_walkers(sid))
+        c2.close()
+    a, b = res
+    assert np.array_equal(a["phi"][:5], b["phi"])
+    assert np.array_equal(a["weight"][:5], b["weight"])
+
+
+def test_run_twice_bitwise(ctx):
+    """Two fresh contexts, same inputs and seed: bitwise identical results
+    (fixed-order reductions, no atomics in the arithmetic)."""
+    import torch
+    from paper_2403_02542_amd import afq
+    case = C.Case.from_config("c1")
+    outs = []
+    for _ in range(2):
+        c2 = afq.Context(0)
+        sid = case.gpu(c2, 16)
+        c2.propagate_batch(sid, tau=0.01, n_steps=5, exp_order=6, seed=3)
+        torch.cuda.synchronize()
+        outs.append((c2.get_walkers(sid), c2.local_energy_batch(sid)))
+        c2.close()
+    assert np.array_equal(outs[0][0]["phi"], outs[1][0]["phi"])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_library_rng_trajectory_matches_oracle(ctx):
+    """Fields drawn inside the library (no fields argument) reproduce the
+    oracle run on the generator's fields."""
+    import torch
+    cfg = W.CONFIGS["c1"]
+    case = C.Case.from_config("c1")
+    sid = case.gpu(ctx, cfg.W)        # the Philox key is (seed, system id)
+    eo = torch.zeros((1, 10, 2), dtype=torch.float64, device="cuda")
+    ctx.propagate_batch(sid, tau=cfg.tau, n_steps=10, exp_order=cfg.k, seed=0, energies_out=eo)
+    torch.cuda.synchronize()
+    p = case.oracle(cfg.tau)
+    wks = [O.init_walker(p) for _ in range(cfg.W)]
+    wks, hist = O.run(p, wks, lambda t: W.fields(0, sid, t, cfg.W, cfg.G), 10, O.EXP_KRYLOV,
+                      cfg.k, 1)
+    st = ctx.get_walkers(sid)
+    for w in range(cfg.W):
+        assert C.rel(st["phi"][w], wks[w].phi) < 1e-9
+    est = eo.cpu().numpy()[0]
+    for s in range(10):
+        num, den = hist[s]["estimator"]
+        assert abs(est[s, 0] - num) < 1e-9 * abs(num)
+        assert abs(est[s, 1] - den) < 1e-9 * abs(den)
+
+
+def test_caps_and_frozen_walkers(ctx):
+    """Crafted cases: walkers far from the trial at a large tau make force-bias
+    components reach |f| >= 1 (capped to 0); enormous fields overflow one
+    walker, which is frozen with weight 0 and its state held."""
+    import torch
+    case = C.Case.random(20, 4, 30, seed=9, sigma_A=0.3)
+    rng = np.random.default_rng(4)
+    nw = 4
+    phi0 = case.psi[None] + 0.5 * (rng.normal(size=(nw, 20, 4)) + 1j * rng.normal(size=(nw, 20, 4)))
+    sid = case.gpu(ctx, nw, phi0)
+    p = case.oracle(2.0)
+    x = W.fields(1, 0, 0, nw, case.G)
+    x[3, :] = 1e200
+    before = ctx.get_walkers(sid)
+    # no reorthonormalisation: at this tau the propagated orbitals are close to
+    # rank deficient, and their QR factors are not comparable column by column
+    ctx.propagate_batch(sid, tau=2.0, n_steps=1, exp_method=O.EXP_TAYLOR, exp_order=6,
+                        reorth_every=0, fields=C.to_dev(x), e0=p.e0)
+    torch.cuda.synchronize()
+    st = ctx.get_walkers(sid)
+    cnt = ctx.get_counters(sid)
+    assert st["alive"][3] == 0 and st["weight"][3] == 0.0
+    assert np.array_equal(st["phi"][3], before["phi"][3])
+    assert cnt["frozen"] == 1
+    n_exp = 0
+    for w in range(nw):
+        wk0 = O.init_walker(p, phi0[w])
+        f, _ = O.force_bias(p, O.coulomb_vector(p, wk0.theta))
+        n_exp += int(np.sum(np.abs(f) >= 1.0))
+        if w == 3:
+            continue
+        with np.errstate(all="ignore"):
+            wk, info = O.walker_step(p, wk0, x[w], O.EXP_TAYLOR, 6, False)
+        if C.flags_from_info(p, info):
+            continue
+        assert C.rel(st["phi"][w], wk.phi) < C.RTOL
+        assert abs(st["weight"][w] - wk.weight) < C.RTOL * max(1.0, wk.weight)
+    assert n_exp > 0
+    assert cnt["capped_f"] == n_exp
+
+
+def test_reorthonormalisation_ill_conditioned(ctx):
+    """QR of walkers with condition numbers up to 1e7: orthonormal Q, the
+    unique positive-diagonal factor (numpy QR with phases fixed), and the
+    log-overlap lowered by log det R; Green's function and E_L unchanged."""
+    import torch
+    case = C.Case.random(40, 6, 20, seed=13, sigma_A=0.05)
+    rng = np.random.default_rng(5)
+    nw = 6
+    phi0 = np.empty((nw, 40, 6), dtype=complex)
+    for w in range(nw):
+        U, _ = np.linalg.qr(rng.normal(size=(40, 6)) + 1j * rng.normal(size=(40, 6)))
+        V, _ = np.linalg.qr(rng.normal(size=(6, 6)) + 1j * rng.normal(size=(6, 6)))
+        sv = np.logspace(0, -w - 2, 6)
+        phi0[w] = case.psi + 0.01 * (U * sv) @ V
+        phi0[w] = phi0[w] @ np.diag(np.logspace(0, -w - 1, 6))
+    sid = case.gpu(ctx, nw, phi0)
+    p = case.oracle(1e-8)
+    before = ctx.get_walkers(sid)
+    el0 = ctx.local_energy_batch(sid)
+    zero = C.to_dev(np.zeros((1, nw, case.G)))
+    # a tiny tau and zero fields make the step nearly the identity; the QR is what changes
+    ctx.propagate_batch(sid, tau=1e-8, n_steps=1, exp_method=O.EXP_TAYLOR, exp_order=4,
+                        reorth_every=1, fields=zero, e0=p.e0)
+    torch.cuda.synchronize()
+    st = ctx.get_walkers(sid)
+    el1 = ctx.local_energy_batch(sid)
+    for w in range(nw):
+        wk, info = O.walker_step(p, O.init_walker(p, phi0[w]), np.zeros(case.G), O.EXP_TAYLOR,
+                                 4, True)
+        q = st["phi"][w]
+        assert np.abs(q.conj().T @ q - np.eye(6)).max() < 1e-12
+        cond = np.linalg.cond(phi0[w])
+        assert C.rel(q, wk.phi) < 1e-15 * cond * 100, (w, cond)
+        assert abs(st["log_ovlp"][w].real - wk.logdet.real) < 1e-12 * max(1, abs(wk.logdet.real))
+        assert abs(el1[w] - el0[w]) < 1e-9 * abs(el0[w])
+
+
+def test_argument_errors(ctx):
+    from paper_2403_02542_amd import afq
+    h = np.eye(4)
+    L = np.zeros((2, 4, 4))
+    L[0, 0, 1] = 1.0                      # not symmetric
+    with pytest.raises(afq.AfqError) as e:
+        ctx.init_hamiltonian(h, L)
+    assert e.value.code == afq.EINVAL
+    L[0, 1, 0] = 1.0
+    sid = ctx.init_hamiltonian(h, L)
+    with pytest.raises(afq.AfqError) as e:
+        ctx.init_walkers(sid, 4)
+    assert e.value.code == afq.ESTATE
+    with pytest.raises(afq.AfqError):
+        ctx.init_trial(sid, np.ones((4, 2)))     # not orthonormal
+    ctx.init_trial(sid, np.eye(4)[:, :2])
+    ctx.init_walkers(sid, 2)
+    with pytest.raises(afq.AfqError):
+        ctx.propagate_batch(sid, tau=-1.0, n_steps=1)
+    with pytest.raises(afq.AfqError):
+        ctx.propagate_batch(sid, tau=0.1, n_steps=1, exp_order=99)
