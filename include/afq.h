@@ -46,7 +46,11 @@ enum {
   AFQ_ENUMERIC = 5  /* every walker of a system is non-finite                   */
 };
 enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1 };
-enum { AFQ_PREC_FP64 = 0, AFQ_PREC_MIXED = 1 };
+/* Precision of the dense contractions: FP64, or BF16-split operands on the
+ * BF16 matrix cores with FP32 accumulation, three pieces per value (six
+ * piece products, ~24 significand bits) or two pieces (three products, ~16
+ * bits).  Overlap, inverse, QR, weights and energy sums stay FP64. */
+enum { AFQ_PREC_FP64 = 0, AFQ_PREC_MIXED = 1, AFQ_PREC_MIXED_FAST = 2 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
  * enqueue on, or NULL for a stream owned by the context (default priority). */
@@ -87,7 +91,7 @@ typedef struct {
   int32_t exp_method;    /* AFQ_EXP_KRYLOV or AFQ_EXP_TAYLOR                   */
   int32_t exp_order;     /* k: Krylov dimension / Taylor order (1..16)            */
   int32_t reorth_every;  /* QR after global step t when (t+1) % reorth_every == 0 */
-  int32_t precision;     /* AFQ_PREC_FP64 or AFQ_PREC_MIXED                       */
+  int32_t precision;     /* AFQ_PREC_FP64, AFQ_PREC_MIXED or AFQ_PREC_MIXED_FAST   */
   int32_t n_steps;       /* steps to run                                         */
   int32_t energy_every;  /* 1 = local energy every step (0 is read as 1)         */
   double e0;             /* energy shift E0; NaN = trial energy (fixed)          */
@@ -115,9 +119,10 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
 
 /* Local energy of every walker (Eq. eloc) at its current determinant:
  * eloc_out complex128 [W].  The Coulomb vector ell_g = <Lhat_g>_mixed,
- * complex128 [W][n_chol], is written to ell_out if it is not NULL. */
-afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, double* eloc_out,
-                                  double* ell_out, int ptr_is_device);
+ * complex128 [W][n_chol], is written to ell_out if it is not NULL.
+ * precision: AFQ_PREC_* of the contraction (FP64 or BF16-split). */
+afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precision,
+                                  double* eloc_out, double* ell_out, int ptr_is_device);
 
 /* Adjoint of the local energy at fixed walkers and fixed Psi_T:
  * grad_h[M][M]      = sum_w dE_dEL[w] d Re E_L^w / d h,

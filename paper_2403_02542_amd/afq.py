@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libafq.so"
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = range(6)
 EXP_KRYLOV, EXP_TAYLOR = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED_FAST = 0, 1, 2
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENUMERIC"}
 
 EXPORTED = (
@@ -70,7 +70,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "afq_init_trial": (i32, [P, i32, i64, i64, P, ctypes.c_int]),
         "afq_init_walkers": (i32, [P, i32, i64, P, ctypes.c_int]),
         "afq_propagate_batch": (i32, [P, ctypes.POINTER(i32), i32, ctypes.POINTER(PropParams)]),
-        "afq_local_energy_batch": (i32, [P, i32, P, P, ctypes.c_int]),
+        "afq_local_energy_batch": (i32, [P, i32, i32, P, P, ctypes.c_int]),
         "afq_local_energy_adjoint": (i32, [P, i32, P, P, P, ctypes.c_int]),
         "afq_force_bias_adjoint": (i32, [P, i32, P, P, ctypes.c_int]),
         "afq_get_walkers": (i32, [P, i32, P, P, P, P, ctypes.c_int]),
@@ -190,7 +190,7 @@ class Context:
                          math.nan if e0 is None else float(e0), int(seed), int(step0), fp, ep)
         self._check(self._lib.afq_propagate_batch(self._h, arr, len(ids), ctypes.byref(prm)))
 
-    def local_energy_batch(self, sys_id: int, eloc_out=None, ell_out=None):
+    def local_energy_batch(self, sys_id: int, eloc_out=None, ell_out=None, precision=PREC_FP64):
         W, G = self.dims[sys_id]["W"], self.dims[sys_id]["G"]
         host = eloc_out is None or not _is_torch(eloc_out)
         if eloc_out is None:
@@ -199,7 +199,8 @@ class Context:
                 ell_out = np.empty((W, G), dtype=np.complex128)
         ep, edev, _ = _arg(eloc_out, np.complex128)
         lp, ldev, _ = _arg(ell_out if ell_out is not True else None, np.complex128)
-        self._check(self._lib.afq_local_energy_batch(self._h, sys_id, ep, lp, edev))
+        self._check(self._lib.afq_local_energy_batch(self._h, sys_id, int(precision), ep, lp,
+                                                     edev))
         if host:
             return (eloc_out, ell_out) if ell_out is not None else eloc_out
         return eloc_out

@@ -194,3 +194,163 @@ AFQ_DEV void stage_rows_kmajor(double* S, int k0, int K, int nvalid, Get get) {
     S[r * kLDK + k] = v;
   }
 }
+
+// ---------------------------------------------------------------- pipelined engine
+// Workgroup of WR x WC waves computing C[r][c] = sum_k A(r, k) B(c, k) for
+// r < WR*RT*16, c < WC*CT*16.  The TR valid row tiles are split evenly over
+// the WR wave rows (at most RT each) and the TC valid column tiles over the
+// WC wave columns (at most CT each).  K runs in chunks of 16 through two LDS
+// stages: chunk c+1 is fetched from global memory into registers while the
+// MFMAs of chunk c run, then stored into the other stage (one barrier per
+// chunk).  A_KM / B_KM: the operand is stored k-major (consecutive r
+// contiguous); consecutive threads then walk r instead of k.
+template <int WR, int WC, int RT, int CT>
+struct Pipe {
+  static constexpr int NW = WR * WC;
+  static constexpr int NT = NW * 64;
+  static constexpr int ROWS = WR * RT * 16;
+  static constexpr int COLS = WC * CT * 16;
+  static constexpr int STAGE = (ROWS + COLS) * kLDK;   // doubles per stage
+  static constexpr int TOT = (ROWS + COLS) * kBK;
+  static constexpr int PF = (TOT + NT - 1) / NT;
+  static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
+};
+
+struct PipeSplit {
+  int rt0, mtv, ct0, ntv;
+};
+
+template <int WR, int WC, int RT, int CT, bool A_KM, bool B_KM, class GA, class GB>
+AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
+                            d4_t (&acc)[RT][CT]) {
+  using P = Pipe<WR, WC, RT, CT>;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int TR = (nr + 15) >> 4, TC = (nc + 15) >> 4;
+  const int rpw = (TR + WR - 1) / WR, cpw = (TC + WC - 1) / WC;
+  PipeSplit sp;
+  sp.rt0 = wr * rpw;
+  sp.mtv = max(0, min(min(rpw, RT), TR - sp.rt0));
+  sp.ct0 = wc * cpw;
+  sp.ntv = max(0, min(min(cpw, CT), TC - sp.ct0));
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+  double pf[P::PF];
+  auto slot = [&](int e, int& row, int& k) {   // staging element -> (stage row, k)
+    if (e < P::ROWS * kBK) {
+      if (A_KM) {
+        k = e / P::ROWS;
+        row = e - k * P::ROWS;
+      } else {
+        row = e >> 4;
+        k = e & 15;
+      }
+    } else {
+      const int e2 = e - P::ROWS * kBK;
+      int c;
+      if (B_KM) {
+        k = e2 / P::COLS;
+        c = e2 - k * P::COLS;
+      } else {
+        c = e2 >> 4;
+        k = e2 & 15;
+      }
+      row = P::ROWS + c;
+    }
+  };
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < P::PF; ++i) {
+      const int e = tid + i * P::NT;
+      double v = 0.0;
+      if (e < P::TOT) {
+        int row, k;
+        slot(e, row, k);
+        const int kg = k0 + k;
+        if (kg < K) {
+          if (row < P::ROWS) {
+            if (row < nr) v = ga(row, kg);
+          } else if (row - P::ROWS < nc) {
+            v = gb(row - P::ROWS, kg);
+          }
+        }
+      }
+      pf[i] = v;
+    }
+  };
+  auto store = [&](double* S) {
+#pragma unroll
+    for (int i = 0; i < P::PF; ++i) {
+      const int e = tid + i * P::NT;
+      if (e < P::TOT) {
+        int row, k;
+        slot(e, row, k);
+        S[row * kLDK + k] = pf[i];
+      }
+    }
+  };
+  const int nchunk = (K + kBK - 1) / kBK;
+  const int lr = lane & 15, lk = lane >> 4;
+  fetch(0);
+  store(smem);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const double* As = smem + (ch & 1) * P::STAGE;
+    const double* Bs = As + P::ROWS * kLDK;
+    if (ch + 1 < nchunk) fetch((ch + 1) * kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 4) {
+      double a[RT], b[CT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+        a[i] = i < sp.mtv ? As[((sp.rt0 + i) * 16 + lr) * kLDK + kk + lk] : 0.0;
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+        b[j] = j < sp.ntv ? Bs[((sp.ct0 + j) * 16 + lr) * kLDK + kk + lk] : 0.0;
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        if (i < sp.mtv) {
+#pragma unroll
+          for (int j = 0; j < CT; ++j)
+            if (j < sp.ntv) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+        }
+      }
+    }
+    if (ch + 1 < nchunk) store(smem + ((ch + 1) & 1) * P::STAGE);
+    __syncthreads();
+  }
+  return sp;
+}
+
+// Row / column (within the tile) of accumulator element e of tile (i, j).
+AFQ_DEV int pipe_row(const PipeSplit& sp, int i, int e) {
+  return (sp.rt0 + i) * 16 + 4 * e + ((threadIdx.x & 63) >> 4);
+}
+AFQ_DEV int pipe_col(const PipeSplit& sp, int j) { return (sp.ct0 + j) * 16 + (threadIdx.x & 15); }
+
+// ---------------------------------------------------------------- BF16 split
+// A float64 value x is carried as P bfloat16 pieces x = x0 + x1 (+ x2) + r,
+// x_{i+1} = bf16(x - x0 - ... - x_i) (round to nearest even); two pieces keep
+// 16 significand bits, three keep 24.  Products a b are formed from the
+// piece products that matter at that precision (3 for two pieces: a0b0,
+// a0b1, a1b0; 6 for three: + a1b1, a0b2, a2b0) on the BF16 matrix cores,
+// accumulated in FP32.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+AFQ_DEV unsigned short bf16_bits_rn(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+AFQ_DEV float bf16_bits_to_f(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
+
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l % 16][8 (l / 16) .. +7] and
+// B[8 (l / 16) .. +7][l % 16]; accumulator element i of lane l is
+// C[4 (l / 16) + i][l % 16].
+AFQ_DEV f4_t mfma_bf16(const bf8_t& a, const bf8_t& b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}

@@ -57,6 +57,13 @@ struct SysDev {
   double* oinv = nullptr;     // [W][N][N][2]
   double* est = nullptr;      // [2] estimator scratch
   int* counters = nullptr;    // [4] device counters of the last propagate call
+  // mixed precision (BF16-split) operands
+  int mx_pieces = 0;          // pieces of the current split arrays (0 = none)
+  int Kp = 0;                 // K (= M) padded to a multiple of 32
+  unsigned short* Lxb = nullptr;  // [P][(G+1) N][Kp] pieces of the half-rotated blocks
+  int64_t Lxb_ps = 0;
+  unsigned short* thb = nullptr;  // [P][W 2N][Kp] pieces of Theta
+  int64_t thb_ps = 0;
   std::vector<void*> walker_allocs;
 };
 
@@ -121,6 +128,15 @@ hipError_t launch_from_planar(const double* re, const double* im, int W, int M, 
                               double* out, hipStream_t st);
 hipError_t launch_pack_complex(const double* re, const double* im, int64_t n, int64_t ld_in,
                                int64_t cols, double* out, hipStream_t st);
+// BF16 pieces (see afq_device.h): rows of a float64 matrix, and Theta.
+hipError_t launch_split(const double* in, int64_t R, int K, int64_t ld, int Kp, int P,
+                        int64_t piece_stride, unsigned short* out, hipStream_t st);
+hipError_t launch_split_theta(const double* re, const double* im, int W, int N, int M, int Kp,
+                              int P, int64_t piece_stride, unsigned short* out, hipStream_t st);
+// Mixed-precision local-energy contraction (pieces s.Lxb and tb).
+hipError_t launch_exchange_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps,
+                              double* ell_re, double* ell_im, double* ex_re, double* ex_im,
+                              hipStream_t st);
 // Adjoint kernels.
 hipError_t launch_adjoint(SysDev& s, const double* dE, double* grad_h, double* grad_L,
                           hipStream_t st);

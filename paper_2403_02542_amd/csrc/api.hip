@@ -172,6 +172,26 @@ afq_status ensure_krylov(afq_ctx* ctx, int32_t sid, SysDev& s, int k) {
   return AFQ_OK;
 }
 
+// BF16 pieces of the half-rotated blocks and a Theta piece buffer.
+afq_status ensure_mixed(afq_ctx* ctx, int32_t sid, SysDev& s, int pieces) {
+  if (s.mx_pieces == pieces && s.Lxb && s.thb) return AFQ_OK;
+  auto& own = ctx->sys_allocs[sid];
+  auto& wown = s.walker_allocs;
+  s.Kp = (s.M + 31) / 32 * 32;
+  const int64_t rows = (int64_t)(s.G + 1) * s.N;
+  if (!s.Lxb || s.mx_pieces < pieces) {
+    TRY(dalloc(ctx, own, &s.Lxb, (size_t)3 * rows * s.Kp));
+    s.Lxb_ps = rows * s.Kp;
+  }
+  if (!s.thb) {
+    TRY(dalloc(ctx, wown, &s.thb, (size_t)3 * s.W * 2 * s.N * s.Kp));
+    s.thb_ps = (int64_t)s.W * 2 * s.N * s.Kp;
+  }
+  HIPCHK(launch_split(s.Lx, rows, s.M, s.M, s.Kp, pieces, s.Lxb_ps, s.Lxb, ctx->stream));
+  s.mx_pieces = pieces;
+  return AFQ_OK;
+}
+
 // Local energy and Coulomb vector of the current walkers (Theta in th_*).
 afq_status eval_energy(afq_ctx* ctx, SysDev& s, double e0, double tau) {
   HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
@@ -298,7 +318,14 @@ afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_para
   const int every = P.energy_every > 0 ? P.energy_every : 1;
   {
     Phase ph(ctx, AFQ_PH_EXCHANGE);
-    HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
+    if (P.precision == AFQ_PREC_FP64) {
+      HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
+    } else {
+      HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps,
+                                s.thb, st));
+      HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
+                                st));
+    }
   }
   if ((si + 1) % every == 0 || si + 1 == P.n_steps) {
     Phase ph(ctx, AFQ_PH_ENERGY);
@@ -523,6 +550,8 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   free_all(s.walker_allocs);
   s.kmax = 0;
   s.kb_re = s.kb_im = s.kh = nullptr;
+  s.thb = nullptr;
+  if (s.mx_pieces) s.mx_pieces = -1;  // pieces of L stay; Theta buffer re-made
   auto& own = s.walker_allocs;
   s.W = (int)n_walkers;
   const size_t W = s.W, NM = (size_t)s.N * s.M, G1 = (size_t)s.G + 1, MM = (size_t)s.M * s.M;
@@ -594,7 +623,9 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   if (P->exp_method != AFQ_EXP_KRYLOV && P->exp_method != AFQ_EXP_TAYLOR)
     return fail(ctx, AFQ_EINVAL, "unknown exp_method");
   if (P->exp_order < 1 || P->exp_order > 16) return fail(ctx, AFQ_EINVAL, "exp_order must be in [1, 16]");
-  if (P->precision != AFQ_PREC_FP64) return fail(ctx, AFQ_EINVAL, "precision not available");
+  if (P->precision != AFQ_PREC_FP64 && P->precision != AFQ_PREC_MIXED &&
+      P->precision != AFQ_PREC_MIXED_FAST)
+    return fail(ctx, AFQ_EINVAL, "unknown precision");
   if (P->n_steps < 0) return fail(ctx, AFQ_EINVAL, "n_steps < 0");
   if (P->fields && n_sys != 1) return fail(ctx, AFQ_EINVAL, "explicit fields need a single system");
   HIPCHK(hipSetDevice(ctx->device));
@@ -610,6 +641,8 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
       return fail(ctx, AFQ_EINVAL, "Krylov path supports M <= 512");
     TRY(ensure_half_step(ctx, *ss[i], P->tau));
     if (P->exp_method == AFQ_EXP_KRYLOV) TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
+    if (P->precision != AFQ_PREC_FP64)
+      TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], P->precision == AFQ_PREC_MIXED ? 3 : 2));
     e0[i] = std::isnan(P->e0) ? ss[i]->e_trial : P->e0;
     HIPCHK(hipMemsetAsync(ss[i]->counters, 0, 4 * sizeof(int), ctx->stream));
   }
@@ -620,15 +653,27 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
 }
 
-afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, double* eloc_out, double* ell_out,
-                                  int ptr_is_device) try {
+afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precision,
+                                  double* eloc_out, double* ell_out, int ptr_is_device) try {
   SysDev* sp;
   TRY(get_sys(ctx, sys_id, &sp));
   SysDev& s = *sp;
   if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
   if (!eloc_out) return fail(ctx, AFQ_EINVAL, "null eloc_out");
+  if (precision < AFQ_PREC_FP64 || precision > AFQ_PREC_MIXED_FAST)
+    return fail(ctx, AFQ_EINVAL, "unknown precision");
   HIPCHK(hipSetDevice(ctx->device));
-  TRY(eval_energy(ctx, s, 0.0, 0.0));
+  if (precision == AFQ_PREC_FP64) {
+    TRY(eval_energy(ctx, s, 0.0, 0.0));
+  } else {
+    TRY(ensure_mixed(ctx, sys_id, s, precision == AFQ_PREC_MIXED ? 3 : 2));
+    HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps, s.thb,
+                              ctx->stream));
+    HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
+                              ctx->stream));
+    HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, 0.0, 0.0,
+                         ctx->stream));
+  }
   TRY(copy_out(ctx, eloc_out, s.eloc, (size_t)s.W * 16, ptr_is_device));
   if (ell_out) {
     std::vector<void*> tmp;

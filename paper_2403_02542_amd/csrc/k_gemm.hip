@@ -76,45 +76,39 @@ __global__ __launch_bounds__(256) void k_gemm_generic(GemmArgs g) {
 // ------------------------------------------------------------ one-body step
 // out[(plane, w, j)][p] = sum_q in[(plane, w, j)][q] B[p][q]   (B symmetric)
 
-constexpr int OB_MT = 4, OB_NT = 5;
+using OBP = Pipe<4, 2, 2, 5>;
 
-__global__ __launch_bounds__(256) void k_onebody(int WN, int M, const double* __restrict__ in_re,
-                                                 const double* __restrict__ in_im,
-                                                 const double* __restrict__ Bm,
-                                                 double* __restrict__ out_re,
-                                                 double* __restrict__ out_im) {
-  constexpr int ROWS = 32 * OB_MT, COLS = 32 * OB_NT;
-  __shared__ double As[ROWS * kLDK];
-  __shared__ double Bs[COLS * kLDK];
-  const int nct = (M + COLS - 1) / COLS;
-  const int rt = blockIdx.x / nct, ct = blockIdx.x % nct;
-  const int r0 = rt * ROWS, c0 = ct * COLS;
+__global__ __launch_bounds__(OBP::NT) void k_onebody(int WN, int M, int n_ct,
+                                                     const double* __restrict__ in_re,
+                                                     const double* __restrict__ in_im,
+                                                     const double* __restrict__ Bm,
+                                                     double* __restrict__ out_re,
+                                                     double* __restrict__ out_im) {
+  extern __shared__ double smem[];
+  const int rt = blockIdx.x / n_ct, ct = blockIdx.x % n_ct;
+  const int r0 = rt * OBP::ROWS, c0 = ct * OBP::COLS;
   const int R = 2 * WN;
-  const int nr = min(ROWS, R - r0), nc = min(COLS, M - c0);
-  const WaveSplit ws = wave_split<OB_MT, OB_NT>(nr, nc);
-  TileAcc<OB_MT, OB_NT> acc;
-  acc.zero();
-  auto getA = [&](int r, int k) {
+  const int nr = min(OBP::ROWS, R - r0), nc = min(OBP::COLS, M - c0);
+  auto ga = [&](int r, int k) {
     const int64_t rr = r0 + r;
     return rr < WN ? in_re[rr * M + k] : in_im[(rr - WN) * M + k];
   };
-  auto getB = [&](int c, int k) { return Bm[(int64_t)(c0 + c) * M + k]; };
-  auto fa = [&](int k0, double* S) { stage_rows<ROWS>(S, k0, M, nr, getA); };
-  auto fb = [&](int k0, double* S) { stage_rows<COLS>(S, k0, M, nc, getB); };
-  tile_gemm<OB_MT, OB_NT>(M, ws, fa, fb, As, Bs, acc);
+  auto gb = [&](int c, int k) { return Bm[(int64_t)(c0 + c) * M + k]; };
+  d4_t acc[2][5];
+  const PipeSplit sp = pipe_gemm<4, 2, 2, 5, false, false>(M, nr, nc, ga, gb, smem, acc);
 #pragma unroll
-  for (int i = 0; i < OB_MT; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < OB_NT; ++j) {
-      if (i >= ws.mtv || j >= ws.ntv) continue;
-      const int c = acc_col(ws, j);
+    for (int j = 0; j < 5; ++j) {
+      if (i >= sp.mtv || j >= sp.ntv) continue;
+      const int c = pipe_col(sp, j);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = acc_row(ws, i, e);
+        const int r = pipe_row(sp, i, e);
         if (r < nr && c < nc) {
           const int64_t rr = r0 + r;
-          if (rr < WN) out_re[rr * M + c0 + c] = acc.c[i][j][e];
-          else out_im[(rr - WN) * M + c0 + c] = acc.c[i][j][e];
+          if (rr < WN) out_re[rr * M + c0 + c] = acc[i][j][e];
+          else out_im[(rr - WN) * M + c0 + c] = acc[i][j][e];
         }
       }
     }
@@ -123,48 +117,43 @@ __global__ __launch_bounds__(256) void k_onebody(int WN, int M, const double* __
 // ------------------------------------------------------------ operator build
 // A_plane[w][pq] = sum_g a_plane[w][g] L[g][pq],  a = i sqrt(tau) (x - fbar)
 
-constexpr int OP_MT = 4, OP_NT = 5;
+using OPP = Pipe<4, 2, 2, 4>;
 
-__global__ __launch_bounds__(256) void k_opbuild(int W, int G, int64_t MM,
-                                                 const double* __restrict__ a_re,
-                                                 const double* __restrict__ a_im,
-                                                 const double* __restrict__ L,
-                                                 double* __restrict__ A_re,
-                                                 double* __restrict__ A_im, int n_rt, int n_ct) {
-  constexpr int ROWS = 32 * OP_MT, COLS = 32 * OP_NT;
-  __shared__ double As[ROWS * kLDK];
-  __shared__ double Bs[COLS * kLDK];
+__global__ __launch_bounds__(OPP::NT) void k_opbuild(int W, int G, int64_t MM,
+                                                     const double* __restrict__ a_re,
+                                                     const double* __restrict__ a_im,
+                                                     const double* __restrict__ L,
+                                                     double* __restrict__ A_re,
+                                                     double* __restrict__ A_im, int n_rt,
+                                                     int n_ct) {
+  extern __shared__ double smem[];
   int ct, rt;
   if (!xcd_swizzle(blockIdx.x, n_rt, n_ct, ct, rt)) return;
-  const int r0 = rt * ROWS;
-  const int64_t c0 = (int64_t)ct * COLS;
+  const int r0 = rt * OPP::ROWS;
+  const int64_t c0 = (int64_t)ct * OPP::COLS;
   const int R = 2 * W;
-  const int nr = min(ROWS, R - r0);
-  const int nc = (int)min((int64_t)COLS, MM - c0);
-  const WaveSplit ws = wave_split<OP_MT, OP_NT>(nr, nc);
-  TileAcc<OP_MT, OP_NT> acc;
-  acc.zero();
-  auto getA = [&](int r, int k) {
+  const int nr = min(OPP::ROWS, R - r0);
+  const int nc = (int)min((int64_t)OPP::COLS, MM - c0);
+  auto ga = [&](int r, int k) {
     const int rr = r0 + r;
     return rr < W ? a_re[(int64_t)rr * G + k] : a_im[(int64_t)(rr - W) * G + k];
   };
-  auto getB = [&](int c, int k) { return L[(int64_t)k * MM + c0 + c]; };
-  auto fa = [&](int k0, double* S) { stage_rows<ROWS>(S, k0, G, nr, getA); };
-  auto fb = [&](int k0, double* S) { stage_rows_kmajor<COLS>(S, k0, G, nc, getB); };
-  tile_gemm<OP_MT, OP_NT>(G, ws, fa, fb, As, Bs, acc);
+  auto gb = [&](int c, int k) { return L[(int64_t)k * MM + c0 + c]; };
+  d4_t acc[2][4];
+  const PipeSplit sp = pipe_gemm<4, 2, 2, 4, false, true>(G, nr, nc, ga, gb, smem, acc);
 #pragma unroll
-  for (int i = 0; i < OP_MT; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < OP_NT; ++j) {
-      if (i >= ws.mtv || j >= ws.ntv) continue;
-      const int c = acc_col(ws, j);
+    for (int j = 0; j < 4; ++j) {
+      if (i >= sp.mtv || j >= sp.ntv) continue;
+      const int c = pipe_col(sp, j);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = acc_row(ws, i, e);
+        const int r = pipe_row(sp, i, e);
         if (r < nr && c < nc) {
           const int rr = r0 + r;
-          if (rr < W) A_re[(int64_t)rr * MM + c0 + c] = acc.c[i][j][e];
-          else A_im[(int64_t)(rr - W) * MM + c0 + c] = acc.c[i][j][e];
+          if (rr < W) A_re[(int64_t)rr * MM + c0 + c] = acc[i][j][e];
+          else A_im[(int64_t)(rr - W) * MM + c0 + c] = acc[i][j][e];
         }
       }
     }
@@ -177,7 +166,9 @@ __global__ __launch_bounds__(256) void k_opbuild(int W, int G, int64_t MM,
 //   col p:       [ A_re[p][q],   A_im[p][q] ]
 // mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
 
-constexpr int MV_MT = 5, MV_NT = 4;
+// Four waves side by side over the columns (p); every wave holds all row
+// tiles (2N rows, RT >= ceil(2N / 16)) and up to two column tiles.
+constexpr int MV_WC = 4, MV_CT = 2;
 
 struct VecRef {
   const double* re;
@@ -190,58 +181,54 @@ struct VecOut {
   int64_t sw, sj;
 };
 
-__global__ __launch_bounds__(256) void k_matvec(int W, int N, int M, VecRef v,
-                                                const double* __restrict__ A_re,
-                                                const double* __restrict__ A_im, VecOut o,
-                                                int mode, double inv_n, VecOut sum, int n_ct) {
-  constexpr int ROWS = 32 * MV_MT, COLS = 32 * MV_NT;
-  __shared__ double As[ROWS * kLDK];
-  __shared__ double Bs[COLS * kLDK];
+template <int RT>
+__global__ __launch_bounds__(64 * MV_WC) void k_matvec(int W, int N, int M, VecRef v,
+                                                       const double* __restrict__ A_re,
+                                                       const double* __restrict__ A_im, VecOut o,
+                                                       int mode, double inv_n, VecOut sum,
+                                                       int n_ct) {
+  extern __shared__ double smem[];
   int w, ct;
   if (!xcd_swizzle(blockIdx.x, n_ct, W, w, ct)) return;
   // balanced column blocks: n_ct blocks over ceil(M/16) tiles
-  const int TC = (M + 15) / 16;
-  const int tpb = (TC + n_ct - 1) / n_ct;
+  const int TCt = (M + 15) / 16;
+  const int tpb = (TCt + n_ct - 1) / n_ct;
   const int c0 = ct * tpb * 16;
   if (c0 >= M) return;
   const int nc = min(tpb * 16, M - c0);
   const int nr = 2 * N;
-  const WaveSplit ws = wave_split<MV_MT, MV_NT>(nr, nc);
-  TileAcc<MV_MT, MV_NT> acc;
-  acc.zero();
   const double* vre = v.re + (int64_t)w * v.sw;
   const double* vim = v.im + (int64_t)w * v.sw;
   const int64_t MM = (int64_t)M * M;
   const double* Are = A_re + (int64_t)w * MM;
   const double* Aim = A_im + (int64_t)w * MM;
-  auto getA = [&](int r, int k) {
+  auto ga = [&](int r, int k) {
     const bool im_row = r >= N;
     const int j = im_row ? r - N : r;
     if (k < M) return im_row ? vim[j * v.sj + k] : vre[j * v.sj + k];
     const int q = k - M;
     return im_row ? vre[j * v.sj + q] : -vim[j * v.sj + q];
   };
-  auto getB = [&](int c, int k) {
+  auto gb = [&](int c, int k) {
     const int64_t p = c0 + c;
     return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
   };
-  auto fa = [&](int k0, double* S) { stage_rows<ROWS>(S, k0, 2 * M, nr, getA); };
-  auto fb = [&](int k0, double* S) { stage_rows<COLS>(S, k0, 2 * M, nc, getB); };
-  tile_gemm<MV_MT, MV_NT>(2 * M, ws, fa, fb, As, Bs, acc);
+  d4_t acc[RT][MV_CT];
+  const PipeSplit sp = pipe_gemm<1, MV_WC, RT, MV_CT, false, false>(2 * M, nr, nc, ga, gb, smem, acc);
 #pragma unroll
-  for (int i = 0; i < MV_MT; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
-    for (int jt = 0; jt < MV_NT; ++jt) {
-      if (i >= ws.mtv || jt >= ws.ntv) continue;
-      const int c = acc_col(ws, jt);
+    for (int jt = 0; jt < MV_CT; ++jt) {
+      if (i >= sp.mtv || jt >= sp.ntv) continue;
+      const int c = pipe_col(sp, jt);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = acc_row(ws, i, e);
+        const int r = pipe_row(sp, i, e);
         if (r < nr && c < nc) {
           const bool im_row = r >= N;
           const int j = im_row ? r - N : r;
           const int64_t off = (int64_t)w * o.sw + (int64_t)j * o.sj + c0 + c;
-          double val = acc.c[i][jt][e];
+          double val = acc[i][jt][e];
           if (mode == 1) {
             val *= inv_n;
             const int64_t soff = (int64_t)w * sum.sw + (int64_t)j * sum.sj + c0 + c;
@@ -257,17 +244,34 @@ __global__ __launch_bounds__(256) void k_matvec(int W, int N, int M, VecRef v,
 
 int matvec_col_blocks(int M) {
   const int TC = (M + 15) / 16;
-  const int per = 2 * MV_NT;
+  const int per = MV_WC * MV_CT;
   return (TC + per - 1) / per;
+}
+
+template <int RT>
+hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+                     hipStream_t st) {
+  using P = Pipe<1, MV_WC, RT, MV_CT>;
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
+  const int n_ct = matvec_col_blocks(s.M);
+  hipLaunchKernelGGL(k_matvec<RT>, dim3(xcd_grid(s.W, n_ct)), dim3(P::NT), P::LDS_BYTES, st, s.W,
+                     s.N, s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
+  return hipGetLastError();
 }
 
 hipError_t run_matvec(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                       hipStream_t st) {
-  if (2 * s.N > 32 * MV_MT) return hipErrorInvalidValue;
-  const int n_ct = matvec_col_blocks(s.M);
-  hipLaunchKernelGGL(k_matvec, dim3(xcd_grid(s.W, n_ct)), dim3(256), 0, st, s.W, s.N, s.M, v,
-                     s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
-  return hipGetLastError();
+  const int TR = (2 * s.N + 15) / 16;
+  if (TR <= 4) return matvec_rt<4>(s, v, o, mode, inv_n, sum, st);
+  if (TR <= 7) return matvec_rt<7>(s, v, o, mode, inv_n, sum, st);
+  if (TR <= 10) return matvec_rt<10>(s, v, o, mode, inv_n, sum, st);
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------ Krylov pieces
@@ -491,20 +495,34 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
 
 hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                           double* out_im, hipStream_t st) {
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_onebody,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
   const int WN = s.W * s.N;
-  const int nrt = (2 * WN + 32 * OB_MT - 1) / (32 * OB_MT);
-  const int nct = (s.M + 32 * OB_NT - 1) / (32 * OB_NT);
-  hipLaunchKernelGGL(k_onebody, dim3(nrt * nct), dim3(256), 0, st, WN, s.M, in_re, in_im,
-                     s.Bhalf, out_re, out_im);
+  const int nrt = (2 * WN + OBP::ROWS - 1) / OBP::ROWS;
+  const int nct = (s.M + OBP::COLS - 1) / OBP::COLS;
+  hipLaunchKernelGGL(k_onebody, dim3(nrt * nct), dim3(OBP::NT), OBP::LDS_BYTES, st, WN, s.M, nct,
+                     in_re, in_im, s.Bhalf, out_re, out_im);
   return hipGetLastError();
 }
 
 hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
   const int64_t MM = (int64_t)s.M * s.M;
-  const int n_rt = (2 * s.W + 32 * OP_MT - 1) / (32 * OP_MT);
-  const int n_ct = (int)((MM + 32 * OP_NT - 1) / (32 * OP_NT));
-  hipLaunchKernelGGL(k_opbuild, dim3(xcd_grid(n_ct, n_rt)), dim3(256), 0, st, s.W, s.G, MM,
-                     s.av_re, s.av_im, s.L, s.A_re, s.A_im, n_rt, n_ct);
+  const int n_rt = (2 * s.W + OPP::ROWS - 1) / OPP::ROWS;
+  const int n_ct = (int)((MM + OPP::COLS - 1) / OPP::COLS);
+  hipLaunchKernelGGL(k_opbuild, dim3(xcd_grid(n_ct, n_rt)), dim3(OPP::NT), OPP::LDS_BYTES, st, s.W,
+                     s.G, MM, s.av_re, s.av_im, s.L, s.A_re, s.A_im, n_rt, n_ct);
   return hipGetLastError();
 }
 

@@ -1,0 +1,355 @@
+// Mixed-precision forms of the dense contractions: BF16-split operands on
+// the BF16 matrix cores with FP32 accumulation (see afq_device.h).  FP64
+// stays for everything else: overlap, inverse, QR, weights and the energy
+// sums.
+//
+//  * k_split: float64 planes -> P bfloat16 piece planes, rows padded to Kp.
+//  * k_exchange_mx: the local-energy contraction of k_exchange.hip with the
+//    T_g blocks formed from BF16-split (Psi_T^T L_g) and Theta; the N x N
+//    blocks are reduced in float64 exactly as in the FP64 kernel.
+#include "afq_device.h"
+#include "afq_internal.h"
+
+namespace {
+
+// out[p][r][k] (bf16 bits), r < R, k < Kp: pieces of in[r * ld + k] (0 for k >= K).
+__global__ void k_split(const double* __restrict__ in, int64_t R, int K, int64_t ld, int Kp, int P,
+                        int64_t piece_stride, unsigned short* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R * Kp) return;
+  const int64_t r = e / Kp;
+  const int k = (int)(e - r * Kp);
+  double x = k < K ? in[r * ld + k] : 0.0;
+  for (int p = 0; p < P; ++p) {
+    const unsigned short b = bf16_bits_rn((float)x);
+    out[p * piece_stride + e] = b;
+    x -= (double)bf16_bits_to_f(b);
+  }
+}
+
+// Theta planes [W][N][M] -> pieces of rows (w, plane, j) x Kp.
+__global__ void k_split_theta(const double* __restrict__ re, const double* __restrict__ im, int W,
+                              int N, int M, int Kp, int P, int64_t piece_stride,
+                              unsigned short* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = (int64_t)W * 2 * N;
+  if (e >= rows * Kp) return;
+  const int64_t r = e / Kp;
+  const int k = (int)(e - r * Kp);
+  const int64_t w = r / (2 * N);
+  const int rem = (int)(r - w * 2 * N);
+  const int pl = rem >= N, j = pl ? rem - N : rem;
+  const double* src = pl ? im : re;
+  double x = k < M ? src[(w * N + j) * M + k] : 0.0;
+  for (int p = 0; p < P; ++p) {
+    const unsigned short b = bf16_bits_rn((float)x);
+    out[p * piece_stride + e] = b;
+    x -= (double)bf16_bits_to_f(b);
+  }
+}
+
+constexpr int MW = 8;                      // waves
+constexpr int MT_ = MW * 64;               // threads
+constexpr int M_RT = 2;                    // row tiles per wave
+constexpr int M_ROWS = MW * M_RT * 16;     // 256
+constexpr int M_KC = 32;                   // K per chunk (one MFMA k-step)
+constexpr int M_PITCH = 40;                // bf16 per staged row (32 + 8 pad)
+constexpr int M_SUPER_G = 4, M_SUPER_W = 8;
+
+template <int P>
+struct MxProds;
+template <>
+struct MxProds<2> {
+  static constexpr int N = 3;
+  static constexpr int a[3] = {0, 0, 1};
+  static constexpr int b[3] = {0, 1, 0};
+};
+template <>
+struct MxProds<3> {
+  static constexpr int N = 6;
+  static constexpr int a[6] = {0, 0, 1, 1, 0, 2};
+  static constexpr int b[6] = {0, 1, 0, 1, 2, 0};
+};
+
+// Lb: P pieces of the (G+1) N x Kp half-rotated blocks; tb: P pieces of
+// Theta as rows (w, plane, j) x Kp.
+//
+// Each wave owns its row tiles outright, so their fragments are loaded from
+// global memory straight into registers (next chunk prefetched); only the
+// column operand, which every wave reads, is staged in LDS (double buffer,
+// register prefetch, one barrier per chunk).
+template <int CT, int P>
+__global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int W, int GA, int WB,
+                                                     int n_gt, int n_wt, int grp, int red_off,
+                                                     const unsigned short* __restrict__ Lb,
+                                                     int64_t Lb_ps,
+                                                     const unsigned short* __restrict__ tb,
+                                                     int64_t tb_ps, double* __restrict__ ell_re,
+                                                     double* __restrict__ ell_im,
+                                                     double* __restrict__ ex_re,
+                                                     double* __restrict__ ex_im) {
+  extern __shared__ double smem[];
+  unsigned short* lds = (unsigned short*)smem;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int id = blockIdx.x;
+  const int xcd = id & 7, slot = id >> 3;
+  const int per = M_SUPER_G * M_SUPER_W;
+  const int sidx = (slot / per) * 8 + xcd, local = slot % per;
+  const int n_sw = (n_wt + M_SUPER_W - 1) / M_SUPER_W;
+  const int gt = (sidx / n_sw) * M_SUPER_G + local / M_SUPER_W;
+  const int wt = (sidx % n_sw) * M_SUPER_W + local % M_SUPER_W;
+  if (gt >= n_gt || wt >= n_wt) return;
+  const int g0 = gt * GA, w0 = wt * WB;
+  const int ga = min(GA, G1 - g0), wb = min(WB, W - w0);
+  const int nr = ga * N, twoN = 2 * N, nc = wb * twoN;
+  const int TR = (nr + 15) >> 4, TC = (nc + 15) >> 4;
+  const int rpw = (TR + MW - 1) / MW;
+  const int rt0 = wave * rpw;
+  const int mtv = max(0, min(rpw, TR - rt0));
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+
+  // ---- row operand: this lane's fragment rows, straight from global memory
+  const int64_t a_row0 = (int64_t)g0 * N;
+  bool arow_ok[M_RT];
+  const unsigned short* aptr[M_RT];
+#pragma unroll
+  for (int i = 0; i < M_RT; ++i) {
+    const int r = (rt0 + i) * 16 + lr;
+    arow_ok[i] = (i < mtv) && (r < nr);
+    aptr[i] = Lb + (a_row0 + (arow_ok[i] ? r : 0)) * Kp + lk;
+  }
+  uint4 afr[M_RT][P];
+  auto fetch_a = [&](int k0, uint4 (&dst)[M_RT][P]) {
+#pragma unroll
+    for (int i = 0; i < M_RT; ++i)
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        dst[i][p] = arow_ok[i] ? *(const uint4*)(aptr[i] + p * Lb_ps + k0) : make_uint4(0, 0, 0, 0);
+  };
+
+  // ---- column operand: staged in LDS, [stage][p][col][M_PITCH]
+  constexpr int BROWS = CT * 16;
+  constexpr int BSTAGE = P * BROWS * M_PITCH;      // bf16 per stage
+  constexpr int UNITS = BROWS * P * (M_KC / 8);    // 16-byte units per chunk
+  constexpr int PFU = (UNITS + MT_ - 1) / MT_;
+  const int64_t b_row0 = (int64_t)w0 * twoN;
+  uint4 pf[PFU];
+  auto fetch_b = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < PFU; ++i) {
+      const int u = tid + i * MT_;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (u < UNITS) {
+        const int k8 = u & 3, rp = u >> 2, p = rp % P, c = rp / P;
+        if (c < nc) v = *(const uint4*)(tb + p * tb_ps + (b_row0 + c) * Kp + k0 + k8 * 8);
+      }
+      pf[i] = v;
+    }
+  };
+  auto store_b = [&](unsigned short* S) {
+#pragma unroll
+    for (int i = 0; i < PFU; ++i) {
+      const int u = tid + i * MT_;
+      if (u < UNITS) {
+        const int k8 = u & 3, rp = u >> 2, p = rp % P, c = rp / P;
+        *(uint4*)(S + ((size_t)p * BROWS + c) * M_PITCH + k8 * 8) = pf[i];
+      }
+    }
+  };
+
+  f4_t acc[M_RT][CT];
+#pragma unroll
+  for (int i = 0; i < M_RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int nchunk = Kp / M_KC;
+  fetch_a(0, afr);
+  fetch_b(0);
+  store_b(lds);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const unsigned short* Bs = lds + (ch & 1) * BSTAGE;
+    uint4 anx[M_RT][P];
+    const bool more = ch + 1 < nchunk;
+    if (more) {
+      fetch_a((ch + 1) * M_KC, anx);
+      fetch_b((ch + 1) * M_KC);
+    }
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      if (j >= TC) continue;
+      bf8_t b[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        b[p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + j * 16 + lr) * M_PITCH + lk);
+#pragma unroll
+      for (int i = 0; i < M_RT; ++i) {
+        if (i >= mtv) continue;
+#pragma unroll
+        for (int q = 0; q < MxProds<P>::N; ++q) {
+          const uint4 av = afr[i][MxProds<P>::a[q]];
+          acc[i][j] = mfma_bf16(*(const bf8_t*)&av, b[MxProds<P>::b[q]], acc[i][j]);
+        }
+      }
+    }
+    if (more) {
+      store_b(lds + ((ch + 1) & 1) * BSTAGE);
+#pragma unroll
+      for (int i = 0; i < M_RT; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) afr[i][p] = anx[i][p];
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue (as in the FP64 kernel), T in float64
+  double* Ts = smem;
+  double* red = smem + red_off;               // partial sums [gl][wave][4]
+  const int ldt = twoN + 1;
+  for (int wl = 0; wl < wb; ++wl) {
+    for (int gb = 0; gb < ga; gb += grp) {
+      const int gn = min(grp, ga - gb);
+      const int rlo = gb * N, rhi = (gb + gn) * N;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < M_RT; ++i) {
+        if (i >= mtv) continue;
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+          if (j >= TC) continue;
+          const int c = j * 16 + lr - wl * twoN;
+          if (c < 0 || c >= twoN) continue;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = (rt0 + i) * 16 + (lane >> 4) * 4 + e;
+            if (r >= rlo && r < rhi) Ts[(r - rlo) * ldt + c] = (double)acc[i][j][e];
+          }
+        }
+      }
+      __syncthreads();
+      for (int gl = 0; gl < gn; ++gl) {
+        const double* T = Ts + (int64_t)gl * N * ldt;
+        double xr = 0.0, xi = 0.0, tr = 0.0, ti = 0.0;
+        for (int e = tid; e < N * N; e += MT_) {
+          const int i = e / N, j = e - i * N;
+          const double ar = T[i * ldt + j], ai = T[i * ldt + N + j];
+          const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
+          xr += ar * br - ai * bi;
+          xi += ar * bi + ai * br;
+          if (i == j) {
+            tr += ar;
+            ti += ai;
+          }
+        }
+        xr = wave_sum(xr);
+        xi = wave_sum(xi);
+        tr = wave_sum(tr);
+        ti = wave_sum(ti);
+        if (lane == 0) {
+          double* rr = red + (gl * MW + wave) * 4;
+          rr[0] = xr;
+          rr[1] = xi;
+          rr[2] = tr;
+          rr[3] = ti;
+        }
+      }
+      __syncthreads();
+      if (tid < gn) {
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < MW; ++v)
+          for (int q = 0; q < 4; ++q) s[q] += red[(tid * MW + v) * 4 + q];
+        const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb + tid;
+        ex_re[o] = s[0];
+        ex_im[o] = s[1];
+        ell_re[o] = 2.0 * s[2];
+        ell_im[o] = 2.0 * s[3];
+      }
+    }
+  }
+}
+
+void exchange_mx_tile(int N, int& GA, int& WB) {
+  double best = -1.0;
+  GA = 1;
+  WB = 1;
+  for (int ga = 1; ga * N <= M_ROWS; ++ga)
+    for (int wb = 1; wb * 2 * N <= 160; ++wb) {
+      const int TR = (ga * N + 15) / 16, TC = (wb * 2 * N + 15) / 16;
+      const int rpw = (TR + MW - 1) / MW;
+      if (rpw > M_RT || TC > 10) continue;
+      const double useful = (double)ga * N * wb * 2 * N;
+      const double work = (double)MW * rpw * TC * 256.0;
+      const double eff = useful / work + 1e-6 * ga * wb;
+      if (eff > best) {
+        best = eff;
+        GA = ga;
+        WB = wb;
+      }
+    }
+}
+
+template <int CT, int P>
+hipError_t launch_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps, double* ell_re,
+                     double* ell_im, double* ex_re, double* ex_im, int GA, int WB, hipStream_t st) {
+  const int N = s.N, G1 = s.G + 1;
+  const int n_gt = (G1 + GA - 1) / GA, n_wt = (W + WB - 1) / WB;
+  const int n_sg = (n_gt + M_SUPER_G - 1) / M_SUPER_G;
+  const int n_sw = (n_wt + M_SUPER_W - 1) / M_SUPER_W;
+  const int grid = ((n_sg * n_sw + 7) / 8) * 8 * M_SUPER_G * M_SUPER_W;
+  // LDS: two B stages; the epilogue reuses it for T (grp blocks) + partials
+  const int red_d = 4 * MW * 32;
+  const size_t stage_doubles = ((size_t)2 * P * CT * 16 * M_PITCH * 2 + 7) / 8;
+  const size_t t_need = (size_t)N * (2 * N + 1) * 2 + red_d;   // at least two blocks
+  const size_t lds_doubles = stage_doubles > t_need ? stage_doubles : t_need;
+  int grp = (int)((lds_doubles - red_d) / ((size_t)N * (2 * N + 1)));
+  if (grp > 32) grp = 32;
+  if (grp < 1 || lds_doubles * 8 > 160 * 1024) return hipErrorInvalidValue;
+  const int red_off = (int)(lds_doubles - red_d);
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_exchange_mx<CT, P>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
+  hipLaunchKernelGGL((k_exchange_mx<CT, P>), dim3(grid), dim3(MT_), lds_doubles * 8, st, G1, N,
+                     s.Kp, W, GA, WB, n_gt, n_wt, grp, red_off, s.Lxb, s.Lxb_ps, tb, tb_ps, ell_re, ell_im,
+                     ex_re, ex_im);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_split(const double* in, int64_t R, int K, int64_t ld, int Kp, int P,
+                        int64_t piece_stride, unsigned short* out, hipStream_t st) {
+  const int64_t n = R * Kp;
+  hipLaunchKernelGGL(k_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, R, K, ld, Kp,
+                     P, piece_stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_theta(const double* re, const double* im, int W, int N, int M, int Kp,
+                              int P, int64_t piece_stride, unsigned short* out, hipStream_t st) {
+  const int64_t n = (int64_t)W * 2 * N * Kp;
+  hipLaunchKernelGGL(k_split_theta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, re, im, W,
+                     N, M, Kp, P, piece_stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps,
+                              double* ell_re, double* ell_im, double* ex_re, double* ex_im,
+                              hipStream_t st) {
+  if (2 * s.N > 160 || !s.Lxb) return hipErrorInvalidValue;
+  int GA, WB;
+  exchange_mx_tile(s.N, GA, WB);
+  const int TC = (WB * 2 * s.N + 15) / 16;
+  if (s.mx_pieces == 3) {
+    if (TC <= 4) return launch_mx<4, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+    if (TC <= 7) return launch_mx<7, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+    return launch_mx<10, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+  }
+  if (TC <= 4) return launch_mx<4, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+  if (TC <= 7) return launch_mx<7, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+  return launch_mx<10, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+}
