@@ -199,19 +199,20 @@ AFQ_DEV void stage_rows_kmajor(double* S, int k0, int K, int nvalid, Get get) {
 // Workgroup of WR x WC waves computing C[r][c] = sum_k A(r, k) B(c, k) for
 // r < WR*RT*16, c < WC*CT*16.  The TR valid row tiles are split evenly over
 // the WR wave rows (at most RT each) and the TC valid column tiles over the
-// WC wave columns (at most CT each).  K runs in chunks of 16 through two LDS
+// WC wave columns (at most CT each).  K runs in chunks of BK through two LDS
 // stages: chunk c+1 is fetched from global memory into registers while the
 // MFMAs of chunk c run, then stored into the other stage (one barrier per
 // chunk).  A_KM / B_KM: the operand is stored k-major (consecutive r
 // contiguous); consecutive threads then walk r instead of k.
-template <int WR, int WC, int RT, int CT>
+template <int WR, int WC, int RT, int CT, int BK = 16>
 struct Pipe {
   static constexpr int NW = WR * WC;
   static constexpr int NT = NW * 64;
   static constexpr int ROWS = WR * RT * 16;
   static constexpr int COLS = WC * CT * 16;
-  static constexpr int STAGE = (ROWS + COLS) * kLDK;   // doubles per stage
-  static constexpr int TOT = (ROWS + COLS) * kBK;
+  static constexpr int LDK = BK + 1;
+  static constexpr int STAGE = (ROWS + COLS) * LDK;   // doubles per stage
+  static constexpr int TOT = (ROWS + COLS) * BK;
   static constexpr int PF = (TOT + NT - 1) / NT;
   static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
 };
@@ -220,10 +221,11 @@ struct PipeSplit {
   int rt0, mtv, ct0, ntv;
 };
 
-template <int WR, int WC, int RT, int CT, bool A_KM, bool B_KM, class GA, class GB>
+template <int WR, int WC, int RT, int CT, bool A_KM, bool B_KM, int BK = 16, class GA, class GB>
 AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
                             d4_t (&acc)[RT][CT]) {
-  using P = Pipe<WR, WC, RT, CT>;
+  using P = Pipe<WR, WC, RT, CT, BK>;
+  constexpr int LDK = P::LDK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
   const int TR = (nr + 15) >> 4, TC = (nc + 15) >> 4;
@@ -239,23 +241,23 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
     for (int j = 0; j < CT; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
   double pf[P::PF];
   auto slot = [&](int e, int& row, int& k) {   // staging element -> (stage row, k)
-    if (e < P::ROWS * kBK) {
+    if (e < P::ROWS * BK) {
       if (A_KM) {
         k = e / P::ROWS;
         row = e - k * P::ROWS;
       } else {
-        row = e >> 4;
-        k = e & 15;
+        row = e / BK;
+        k = e - row * BK;
       }
     } else {
-      const int e2 = e - P::ROWS * kBK;
+      const int e2 = e - P::ROWS * BK;
       int c;
       if (B_KM) {
         k = e2 / P::COLS;
         c = e2 - k * P::COLS;
       } else {
-        c = e2 >> 4;
-        k = e2 & 15;
+        c = e2 / BK;
+        k = e2 - c * BK;
       }
       row = P::ROWS + c;
     }
@@ -287,28 +289,28 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
       if (e < P::TOT) {
         int row, k;
         slot(e, row, k);
-        S[row * kLDK + k] = pf[i];
+        S[row * LDK + k] = pf[i];
       }
     }
   };
-  const int nchunk = (K + kBK - 1) / kBK;
+  const int nchunk = (K + BK - 1) / BK;
   const int lr = lane & 15, lk = lane >> 4;
   fetch(0);
   store(smem);
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
     const double* As = smem + (ch & 1) * P::STAGE;
-    const double* Bs = As + P::ROWS * kLDK;
-    if (ch + 1 < nchunk) fetch((ch + 1) * kBK);
+    const double* Bs = As + P::ROWS * LDK;
+    if (ch + 1 < nchunk) fetch((ch + 1) * BK);
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 4) {
+    for (int kk = 0; kk < BK; kk += 4) {
       double a[RT], b[CT];
 #pragma unroll
       for (int i = 0; i < RT; ++i)
-        a[i] = i < sp.mtv ? As[((sp.rt0 + i) * 16 + lr) * kLDK + kk + lk] : 0.0;
+        a[i] = i < sp.mtv ? As[((sp.rt0 + i) * 16 + lr) * LDK + kk + lk] : 0.0;
 #pragma unroll
       for (int j = 0; j < CT; ++j)
-        b[j] = j < sp.ntv ? Bs[((sp.ct0 + j) * 16 + lr) * kLDK + kk + lk] : 0.0;
+        b[j] = j < sp.ntv ? Bs[((sp.ct0 + j) * 16 + lr) * LDK + kk + lk] : 0.0;
 #pragma unroll
       for (int i = 0; i < RT; ++i) {
         if (i < sp.mtv) {

@@ -167,8 +167,9 @@ __global__ __launch_bounds__(OPP::NT) void k_opbuild(int W, int G, int64_t MM,
 // mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
 
 // Four waves side by side over the columns (p); every wave holds all row
-// tiles (2N rows, RT >= ceil(2N / 16)) and up to two column tiles.
-constexpr int MV_WC = 4, MV_CT = 2;
+// tiles (2N rows, RT >= ceil(2N / 16)) and up to two column tiles; K runs in
+// chunks of 32 so that each fetch from HBM covers 8 MFMA k-steps.
+constexpr int MV_WR = 1, MV_WC = 4, MV_CT = 2, MV_BK = 32;
 
 struct VecRef {
   const double* re;
@@ -182,7 +183,7 @@ struct VecOut {
 };
 
 template <int RT>
-__global__ __launch_bounds__(64 * MV_WC) void k_matvec(int W, int N, int M, VecRef v,
+__global__ __launch_bounds__(64 * MV_WR * MV_WC) void k_matvec(int W, int N, int M, VecRef v,
                                                        const double* __restrict__ A_re,
                                                        const double* __restrict__ A_im, VecOut o,
                                                        int mode, double inv_n, VecOut sum,
@@ -214,7 +215,8 @@ __global__ __launch_bounds__(64 * MV_WC) void k_matvec(int W, int N, int M, VecR
     return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
   };
   d4_t acc[RT][MV_CT];
-  const PipeSplit sp = pipe_gemm<1, MV_WC, RT, MV_CT, false, false>(2 * M, nr, nc, ga, gb, smem, acc);
+  const PipeSplit sp =
+      pipe_gemm<MV_WR, MV_WC, RT, MV_CT, false, false, MV_BK>(2 * M, nr, nc, ga, gb, smem, acc);
 #pragma unroll
   for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -247,11 +249,12 @@ int matvec_col_blocks(int M) {
   const int per = MV_WC * MV_CT;
   return (TC + per - 1) / per;
 }
+static_assert(MV_WR * MV_WC * 64 <= 1024, "workgroup size");
 
 template <int RT>
 hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                      hipStream_t st) {
-  using P = Pipe<1, MV_WC, RT, MV_CT>;
+  using P = Pipe<MV_WR, MV_WC, RT, MV_CT, MV_BK>;
   static bool lds_ok = false;
   if (!lds_ok) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT>,
@@ -268,9 +271,10 @@ hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecO
 hipError_t run_matvec(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                       hipStream_t st) {
   const int TR = (2 * s.N + 15) / 16;
-  if (TR <= 4) return matvec_rt<4>(s, v, o, mode, inv_n, sum, st);
-  if (TR <= 7) return matvec_rt<7>(s, v, o, mode, inv_n, sum, st);
-  if (TR <= 10) return matvec_rt<10>(s, v, o, mode, inv_n, sum, st);
+  const int rpw = (TR + MV_WR - 1) / MV_WR;
+  if (rpw <= 4) return matvec_rt<4>(s, v, o, mode, inv_n, sum, st);
+  if (rpw <= 7) return matvec_rt<7>(s, v, o, mode, inv_n, sum, st);
+  if (rpw <= 10) return matvec_rt<10>(s, v, o, mode, inv_n, sum, st);
   return hipErrorInvalidValue;
 }
 
@@ -309,10 +313,13 @@ __global__ __launch_bounds__(256) void k_krylov_init(int WN, int M, int kmax, in
   }
 }
 
-// Arnoldi step m: w = A b_m (in wv) is orthogonalised against b_0..b_m by two
-// passes of modified Gram-Schmidt; H[0..m][m] accumulates the projections,
-// H[m+1][m] = ||w|| and b_{m+1} = w / ||w|| unless the residual vanishes
-// against ||A b_m|| (happy breakdown: dim = m + 1, b_{m+1} = 0).
+// Arnoldi step m: w = A b_m (in wv) is orthogonalised against b_0..b_m by
+// modified Gram-Schmidt (each b_i is read once into registers for both its
+// projection and the update), with one more pass when the norm drops below
+// 1/sqrt(2) of its value before the pass (Daniel-Gragg-Kaufman-Stewart);
+// H[0..m][m] accumulates the projections, H[m+1][m] = ||w|| and
+// b_{m+1} = w / ||w|| unless the residual vanishes against ||A b_m||
+// (happy breakdown: dim = m + 1, b_{m+1} = 0).
 __global__ __launch_bounds__(256) void k_krylov_orth(int WN, int M, int kmax, int k, int m,
                                                      const double* __restrict__ wv_re,
                                                      const double* __restrict__ wv_im,
@@ -337,31 +344,30 @@ __global__ __launch_bounds__(256) void k_krylov_orth(int WN, int M, int kmax, in
   double s = 0.0;
 #pragma unroll
   for (int t = 0; t < KV_R; ++t) s += wr[t] * wr[t] + wi[t] * wi[t];
-  const double wnorm = sqrt(wave_sum(s));
+  const double wnorm2 = wave_sum(s);
   double* br = kb_re + (int64_t)o * kmax * M;
   double* bi = kb_im + (int64_t)o * kmax * M;
   double* H = kh + (int64_t)o * kmax * kmax * 2;
+  double before2 = wnorm2, after2 = wnorm2;
   for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && !(after2 < 0.5 * before2)) break;
+    before2 = after2;
     for (int i = 0; i <= m; ++i) {
+      double b_r[KV_R], b_i[KV_R];
       double ar = 0.0, ai = 0.0;
 #pragma unroll
       for (int t = 0; t < KV_R; ++t) {
         const int p = lane + 64 * t;
-        if (p < M) {
-          const double b_r = br[i * M + p], b_i = bi[i * M + p];
-          ar += b_r * wr[t] + b_i * wi[t];
-          ai += b_r * wi[t] - b_i * wr[t];
-        }
+        b_r[t] = p < M ? br[i * M + p] : 0.0;
+        b_i[t] = p < M ? bi[i * M + p] : 0.0;
+        ar += b_r[t] * wr[t] + b_i[t] * wi[t];
+        ai += b_r[t] * wi[t] - b_i[t] * wr[t];
       }
       const double cr = wave_sum(ar), ci = wave_sum(ai);
 #pragma unroll
       for (int t = 0; t < KV_R; ++t) {
-        const int p = lane + 64 * t;
-        if (p < M) {
-          const double b_r = br[i * M + p], b_i = bi[i * M + p];
-          wr[t] -= cr * b_r - ci * b_i;
-          wi[t] -= cr * b_i + ci * b_r;
-        }
+        wr[t] -= cr * b_r[t] - ci * b_i[t];
+        wi[t] -= cr * b_i[t] + ci * b_r[t];
       }
       if (lane == 0) {
         double* h = H + (i * kmax + m) * 2;
@@ -374,13 +380,14 @@ __global__ __launch_bounds__(256) void k_krylov_orth(int WN, int M, int kmax, in
         }
       }
     }
+    s = 0.0;
+#pragma unroll
+    for (int t = 0; t < KV_R; ++t) s += wr[t] * wr[t] + wi[t] * wi[t];
+    after2 = wave_sum(s);
   }
   if (m + 1 >= k) return;
-  s = 0.0;
-#pragma unroll
-  for (int t = 0; t < KV_R; ++t) s += wr[t] * wr[t] + wi[t] * wi[t];
-  const double hn = sqrt(wave_sum(s));
-  const bool brk = !(hn > breakdown_rel * wnorm) || hn == 0.0;
+  const double hn = sqrt(after2);
+  const bool brk = !(hn > breakdown_rel * sqrt(wnorm2)) || hn == 0.0;
   const double inv = brk ? 0.0 : 1.0 / hn;
 #pragma unroll
   for (int t = 0; t < KV_R; ++t) {
