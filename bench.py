@@ -48,6 +48,22 @@ def step_flops_per_walker(M, N, G, k, reorth_every):
     return ex + build + matvec + onebody + arnoldi + overlap + qr
 
 
+def measured_traffic(cfg, precision):
+    """HBM bytes per launch of the local-energy kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a plain-copy
+    calibration), or None when the kernel source has changed since, or the
+    run is not the profiled workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_exchange_c3_fp64_traffic.json")
+    if precision != "fp64" or cfg.name != "c3" or cfg.W != 512 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 _CPU_STATE = {}
 _T0 = time.perf_counter()
 
@@ -111,7 +127,19 @@ def main():
     ap.add_argument("--cpu-procs", type=int, default=None,
                     help="oracle processes for the CPU baseline (default: host cores, <= 16)")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (calibrates the "
+                         "HBM byte counters of a profiler) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
               "walkers shard trivially across GPUs but no multi-GPU path is built.",
@@ -171,7 +199,8 @@ def main():
     ex_avg_s = ex_ms / max(1, ex_n) / 1e3
     achieved = ex_flops / ex_avg_s if ex_avg_s > 0 else 0.0
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                "traffic": measured_traffic(cfg, args.precision),
                 "kernel": "k_exchange", "avg_launch_ms": ex_avg_s * 1e3,
                 "flops_per_launch": ex_flops}
     step_fl = step_flops_per_walker(cfg.M, cfg.N, cfg.G, cfg.k, cfg.reorth_every) * cfg.W
