@@ -159,6 +159,8 @@ class Context:
         self._check(self._lib.afq_init_hamiltonian(self._h, M, L.shape[0], hp, lp,
                                                    float(e_core), hd, ctypes.byref(sid)))
         self.dims[sid.value] = {"M": M, "G": L.shape[0]}
+        if hd:
+            self.dims[sid.value]["src"] = ((h.data_ptr(), h._version), (L.data_ptr(), L._version))
         return sid.value
 
     def init_trial(self, sys_id: int, psi_t, n_beta=None):

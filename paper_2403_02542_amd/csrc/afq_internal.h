@@ -137,10 +137,13 @@ hipError_t launch_split_theta(const double* re, const double* im, int W, int N, 
 hipError_t launch_exchange_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps,
                               double* ell_re, double* ell_im, double* ex_re, double* ex_im,
                               hipStream_t st);
-// Adjoint kernels.
-hipError_t launch_adjoint(SysDev& s, const double* dE, double* grad_h, double* grad_L,
-                          hipStream_t st);
-hipError_t launch_fb_adjoint(SysDev& s, const double* d_ell, double* grad_L, hipStream_t st);
+// Adjoints (device pointers; scratch supplied by the caller):
+// TH [W 2N M], Cb and Ub [gchunk N x W 2N], Db [gchunk N M], Y [N M], Z [gchunk N M].
+hipError_t launch_adjoint_into(SysDev& s, const double* dE, double* grad_h, double* grad_L,
+                               double* TH, double* Cb, double* Ub, double* Db, double* Y,
+                               int gchunk, hipStream_t st);
+hipError_t launch_fb_adjoint_into(SysDev& s, const double* d_ell, double* grad_L, double* TH,
+                                  double* Z, int gchunk, hipStream_t st);
 
 // Host symmetric eigensolver (cyclic Jacobi): a (n x n, row-major) is
 // destroyed; evals ascending, evecs column j = eigenvector j (row-major).

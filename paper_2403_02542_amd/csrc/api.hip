@@ -780,15 +780,81 @@ afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4) {
 }
 
 afq_status afq_local_energy_adjoint(afq_ctx* ctx, int32_t sys_id, const double* dE_dEL,
-                                    double* grad_h, double* grad_L, int ptr_is_device) {
-  (void)sys_id; (void)dE_dEL; (void)grad_h; (void)grad_L; (void)ptr_is_device;
-  return fail(ctx, AFQ_ESTATE, "adjoint not available in this build");
+                                    double* grad_h, double* grad_L, int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  if (!dE_dEL || !grad_h || !grad_L) return fail(ctx, AFQ_EINVAL, "null pointer");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t M = s.M, N = s.N, W = s.W, G = s.G;
+  const size_t cols = W * 2 * N;
+  size_t gchunk = (size_t)(256ull << 20) / (N * cols * 8);
+  if (gchunk < 1) gchunk = 1;
+  if (gchunk > G) gchunk = G;
+  std::vector<void*> tmp;
+  double *TH, *Cb, *Ub, *Db, *Y, *dE, *gh = grad_h, *gL = grad_L;
+  afq_status r = AFQ_OK;
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &TH, cols * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Cb, gchunk * N * cols);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Ub, gchunk * N * cols);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Db, gchunk * N * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Y, N * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &dE, W);
+  if (r == AFQ_OK && !ptr_is_device) r = dalloc(ctx, tmp, &gh, M * M);
+  if (r == AFQ_OK && !ptr_is_device) r = dalloc(ctx, tmp, &gL, G * M * M);
+  if (r == AFQ_OK) r = copy_in(ctx, dE, dE_dEL, W, ptr_is_device);
+  if (r == AFQ_OK) r = eval_energy(ctx, s, 0.0, 0.0);   // ell of the current walkers
+  if (r == AFQ_OK) {
+    const hipError_t e = launch_adjoint_into(s, dE, gh, gL, TH, Cb, Ub, Db, Y, (int)gchunk,
+                                             ctx->stream);
+    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, std::string("adjoint: ") + hipGetErrorString(e));
+  }
+  if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, grad_h, gh, M * M * 8, 0);
+  if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, grad_L, gL, G * M * M * 8, 0);
+  if (r == AFQ_OK) {
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, hipGetErrorString(e));
+  }
+  free_all(tmp);
+  return r;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
 }
 
 afq_status afq_force_bias_adjoint(afq_ctx* ctx, int32_t sys_id, const double* d_ell,
-                                  double* grad_L, int ptr_is_device) {
-  (void)sys_id; (void)d_ell; (void)grad_L; (void)ptr_is_device;
-  return fail(ctx, AFQ_ESTATE, "adjoint not available in this build");
+                                  double* grad_L, int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  if (!d_ell || !grad_L) return fail(ctx, AFQ_EINVAL, "null pointer");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t M = s.M, N = s.N, W = s.W, G = s.G;
+  size_t gchunk = (size_t)(256ull << 20) / (N * M * 8);
+  if (gchunk < 1) gchunk = 1;
+  if (gchunk > G) gchunk = G;
+  std::vector<void*> tmp;
+  double *TH, *Z, *dl, *gL = grad_L;
+  afq_status r = AFQ_OK;
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &TH, W * 2 * N * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Z, gchunk * N * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &dl, W * G * 2);
+  if (r == AFQ_OK && !ptr_is_device) r = dalloc(ctx, tmp, &gL, G * M * M);
+  if (r == AFQ_OK) r = copy_in(ctx, dl, d_ell, W * G * 2, ptr_is_device);
+  if (r == AFQ_OK) {
+    const hipError_t e = launch_fb_adjoint_into(s, dl, gL, TH, Z, (int)gchunk, ctx->stream);
+    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, std::string("adjoint: ") + hipGetErrorString(e));
+  }
+  if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, grad_L, gL, G * M * M * 8, 0);
+  if (r == AFQ_OK) {
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, hipGetErrorString(e));
+  }
+  free_all(tmp);
+  return r;
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
 }
 
 afq_status afq_profile(afq_ctx* ctx, int enable) {
