@@ -64,6 +64,122 @@ def measured_traffic(cfg, precision):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+def adjoint_flops(M, N, G, W):
+    """Algorithmic flops of one call pair afq_local_energy_adjoint +
+    afq_force_bias_adjoint over W walkers: the Coulomb vector of every
+    (g, w) (G x 2W x NM), all T_g^w (2WN x G N x M), the D_g contraction
+    (G N x M x 2WN), the h gradient (W NM + M^2 N), the Coulomb-vector
+    weights (G x NM x 2W) and the two batched Psi_T products (G M^2 N each)."""
+    ell = 2.0 * G * (2 * W) * N * M
+    tg = 2.0 * G * N * (2 * W * N) * M
+    dg = 2.0 * G * N * M * (2 * W * N)
+    gh = 2.0 * W * N * M + 2.0 * M * M * N
+    z = 2.0 * G * N * M * 2 * W
+    psi = 2 * 2.0 * G * M * M * N
+    return ell + tg + dg + gh + z + psi
+
+
+def _oracle_grad_worker(args):
+    """One walker's gradients (local energy and Coulomb vector), repeated for
+    about `budget` seconds after a warm-up call; returns (calls, seconds)."""
+    w, budget = args
+    from threadpoolctl import threadpool_limits
+    from oracle import afq_oracle as O
+    st = _CPU_STATE
+    p, theta = st["p"], st["theta"]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.local_energy_gradient(p, theta)
+        O.coulomb_vector_gradient(p, theta, st["d_ell"])
+        reps = max(1, int(math.ceil(budget / (time.perf_counter() - t0))))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            O.local_energy_gradient(p, theta)
+            O.coulomb_vector_gradient(p, theta, st["d_ell"])
+        return reps, time.perf_counter() - t0
+
+
+def adjoint_bench(args):
+    """Throughput of the hand-written adjoint (local energy and Coulomb
+    vector w.r.t. h and L_g) at the c5 shape, after propagating the walkers
+    away from the trial."""
+    cfg = W.CONFIGS["c5"]
+    log(f"generating workload {cfg.name}")
+    ham, psi = W.make_system(cfg)
+    cpu = None
+    if not args.no_cpu:
+        import multiprocessing as mp
+        from oracle import afq_oracle as O
+        with __import__("threadpoolctl").threadpool_limits(1):
+            p = O.prepare(ham.h, ham.L, ham.e_core, psi, cfg.tau)
+        rng = np.random.default_rng(0)
+        phi = psi + 0.05 * (rng.normal(size=psi.shape) + 1j * rng.normal(size=psi.shape))
+        _CPU_STATE.update(p=p, theta=O.overlap(psi, phi)[1],
+                          d_ell=rng.normal(size=cfg.G) + 1j * rng.normal(size=cfg.G))
+        nproc = args.cpu_procs or max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"CPU oracle gradient baseline on {nproc} processes")
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(nproc) as pool:
+            res = pool.map(_oracle_grad_worker, [(w, 10.0) for w in range(nproc)])
+        wall = time.perf_counter() - t0
+        rate = sum(n / t for n, t in res) / cfg.W
+        calls = sum(n for n, _ in res)
+        cpu = {"value": rate, "unit": "adjoint evaluations/s (all walkers)", "cores": int(nproc),
+               "kind": "oracle",
+               "sample": f"{nproc} processes (one BLAS thread each) x ~10 s of one-walker "
+                         f"gradients (local energy + Coulomb vector), {calls} calls after a "
+                         f"warm-up call each; rate scaled to the {cfg.W}-walker batch; "
+                         f"per-walker time {sum(t for _, t in res) / calls:.2f} s, "
+                         f"wall {wall:.1f} s"}
+    import torch
+    from paper_2403_02542_amd import afq
+    log("initialising the GPU library")
+    ctx = afq.Context(0)
+    sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+    ctx.init_trial(sid, psi)
+    ctx.init_walkers(sid, cfg.W)
+    ctx.propagate_batch(sid, tau=cfg.tau, n_steps=cfg.steps, exp_method=afq.EXP_KRYLOV,
+                        exp_order=cfg.k, reorth_every=cfg.reorth_every, seed=0)
+    ctx.sync()
+    M, G, N, Wk = cfg.M, cfg.G, cfg.N, cfg.W
+    dev = "cuda"
+    dE = torch.full((Wk,), 1.0 / Wk, dtype=torch.float64, device=dev)
+    d_ell = torch.randn((Wk, G), dtype=torch.complex128, device=dev)
+    gh = torch.empty((M, M), dtype=torch.float64, device=dev)
+    gL = torch.empty((G, M, M), dtype=torch.float64, device=dev)
+    gF = torch.empty((G, M, M), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        ctx.local_energy_adjoint(sid, dE, gh, gL)
+        ctx.force_bias_adjoint(sid, d_ell, gF)
+    ctx.sync()
+    log(f"timed: {args.steps} adjoint evaluations")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.local_energy_adjoint(sid, dE, gh, gL)
+        ctx.force_bias_adjoint(sid, d_ell, gF)
+    ctx.sync()
+    dt = (time.perf_counter() - t0) / args.steps
+    fl = adjoint_flops(M, N, G, Wk)
+    out = {
+        "metric": "adjoint evaluations/s at c5 (d<E_L>/dh, d<E_L>/dL_g and the Coulomb-vector "
+                  "adjoint over all walkers)",
+        "value": 1.0 / dt, "unit": "evaluations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random Cholesky Hamiltonian, walkers after "
+                f"{cfg.steps} Krylov steps)",
+        "config": {"workload": f"c5: M={M} N={N} G={G} walkers={Wk}", "M": M, "N": N,
+                   "n_chol": G, "walkers": Wk, "parallelism": "1 GPU"},
+        "roofline": {"bound": "mfma", "achieved": fl / dt / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": fl / dt / PEAK_FP64, "traffic": None,
+                     "kernel": "adjoint call pair (k_adj_t and the sliced D product dominate)",
+                     "flops_per_call": fl},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 _CPU_STATE = {}
 _T0 = time.perf_counter()
 
@@ -130,7 +246,12 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the "
                          "HBM byte counters of a profiler) and exit")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the adjoint entry points at the c5 shape instead of the step")
     args = ap.parse_args()
+    if args.adjoint and args.gpus == 1:
+        adjoint_bench(args)
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe * (1 << 20) // 8

@@ -64,6 +64,10 @@ struct SysDev {
   int64_t Lxb_ps = 0;
   unsigned short* thb = nullptr;  // [P][W 2N][Kp] pieces of Theta
   int64_t thb_ps = 0;
+  // adjoint workspace (allocated on first use, sized for the walker count)
+  double* adj_ws = nullptr;
+  size_t adj_ws_n = 0;        // doubles
+  int adj_gchunk = 0;         // Cholesky blocks per chunk of the adjoint
   std::vector<void*> walker_allocs;
 };
 
@@ -138,10 +142,12 @@ hipError_t launch_exchange_mx(SysDev& s, int W, const unsigned short* tb, int64_
                               double* ell_re, double* ell_im, double* ex_re, double* ex_im,
                               hipStream_t st);
 // Adjoints (device pointers; scratch supplied by the caller):
-// TH [W 2N M], Cb and Ub [gchunk N x W 2N], Db [gchunk N M], Y [N M], Z [gchunk N M].
+// TH [W 2N M], Ub [gchunk N x W 2N], Db [S gchunk N M], Y [N M], ellt [G 2W];
+// the Coulomb-vector adjoint uses Db as its [gchunk N M] scratch.
 hipError_t launch_adjoint_into(SysDev& s, const double* dE, double* grad_h, double* grad_L,
-                               double* TH, double* Cb, double* Ub, double* Db, double* Y,
+                               double* TH, double* Ub, double* Db, double* Y, double* ellt,
                                int gchunk, hipStream_t st);
+int adjoint_nsplit(int M, int N, int W, int gchunk);   // Db holds this many slices
 hipError_t launch_fb_adjoint_into(SysDev& s, const double* d_ell, double* grad_L, double* TH,
                                   double* Z, int gchunk, hipStream_t st);
 

@@ -551,6 +551,8 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   s.kmax = 0;
   s.kb_re = s.kb_im = s.kh = nullptr;
   s.thb = nullptr;
+  s.adj_ws = nullptr;
+  s.adj_ws_n = 0;
   if (s.mx_pieces) s.mx_pieces = -1;  // pieces of L stay; Theta buffer re-made
   auto& own = s.walker_allocs;
   s.W = (int)n_walkers;
@@ -779,6 +781,35 @@ afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4) {
   return AFQ_OK;
 }
 
+// Adjoint workspace of a system, carved as TH [W 2N M] | Ub [gchunk N][W 2N] |
+// Db [S][gchunk N M] | Y [N M] | ellt [G][2W] | dE [W 2 G] (the larger of
+// dE_dEL and d_ell).  The chunk of Cholesky blocks keeps Ub near 2 GiB (long
+// products, few launches; HBM is plentiful).
+afq_status ensure_adjoint(afq_ctx* ctx, SysDev& s, double** TH, double** Ub, double** Db,
+                          double** Y, double** ellt, double** dE) {
+  const size_t M = s.M, N = s.N, W = s.W, G = s.G;
+  const size_t cols = W * 2 * N;
+  size_t gchunk = (size_t)(2ull << 30) / (N * cols * 8);
+  if (gchunk < 1) gchunk = 1;
+  if (gchunk > G) gchunk = G;
+  const size_t S = (size_t)adjoint_nsplit(s.M, s.N, s.W, (int)gchunk);
+  const size_t need = cols * M + gchunk * N * cols + S * gchunk * N * M + N * M + G * 2 * W +
+                      W * 2 * G;
+  if (!s.adj_ws || s.adj_ws_n < need) {
+    TRY(dalloc(ctx, s.walker_allocs, &s.adj_ws, need));
+    s.adj_ws_n = need;
+  }
+  s.adj_gchunk = (int)gchunk;
+  double* p = s.adj_ws;
+  *TH = p; p += cols * M;
+  *Ub = p; p += gchunk * N * cols;
+  *Db = p; p += S * gchunk * N * M;
+  *Y = p; p += N * M;
+  *ellt = p; p += G * 2 * W;
+  *dE = p;
+  return AFQ_OK;
+}
+
 afq_status afq_local_energy_adjoint(afq_ctx* ctx, int32_t sys_id, const double* dE_dEL,
                                     double* grad_h, double* grad_L, int ptr_is_device) try {
   SysDev* sp;
@@ -787,36 +818,26 @@ afq_status afq_local_energy_adjoint(afq_ctx* ctx, int32_t sys_id, const double* 
   if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
   if (!dE_dEL || !grad_h || !grad_L) return fail(ctx, AFQ_EINVAL, "null pointer");
   HIPCHK(hipSetDevice(ctx->device));
-  const size_t M = s.M, N = s.N, W = s.W, G = s.G;
-  const size_t cols = W * 2 * N;
-  size_t gchunk = (size_t)(256ull << 20) / (N * cols * 8);
-  if (gchunk < 1) gchunk = 1;
-  if (gchunk > G) gchunk = G;
+  const size_t M = s.M, W = s.W, G = s.G;
+  double *TH, *Ub, *Db, *Y, *ellt, *dE;
+  TRY(ensure_adjoint(ctx, s, &TH, &Ub, &Db, &Y, &ellt, &dE));
   std::vector<void*> tmp;
-  double *TH, *Cb, *Ub, *Db, *Y, *dE, *gh = grad_h, *gL = grad_L;
+  double *gh = grad_h, *gL = grad_L;
   afq_status r = AFQ_OK;
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &TH, cols * M);
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Cb, gchunk * N * cols);
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Ub, gchunk * N * cols);
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Db, gchunk * N * M);
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Y, N * M);
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &dE, W);
-  if (r == AFQ_OK && !ptr_is_device) r = dalloc(ctx, tmp, &gh, M * M);
+  if (!ptr_is_device) r = dalloc(ctx, tmp, &gh, M * M);
   if (r == AFQ_OK && !ptr_is_device) r = dalloc(ctx, tmp, &gL, G * M * M);
   if (r == AFQ_OK) r = copy_in(ctx, dE, dE_dEL, W, ptr_is_device);
-  if (r == AFQ_OK) r = eval_energy(ctx, s, 0.0, 0.0);   // ell of the current walkers
   if (r == AFQ_OK) {
-    const hipError_t e = launch_adjoint_into(s, dE, gh, gL, TH, Cb, Ub, Db, Y, (int)gchunk,
+    const hipError_t e = launch_adjoint_into(s, dE, gh, gL, TH, Ub, Db, Y, ellt, s.adj_gchunk,
                                              ctx->stream);
     if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, std::string("adjoint: ") + hipGetErrorString(e));
   }
   if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, grad_h, gh, M * M * 8, 0);
   if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, grad_L, gL, G * M * M * 8, 0);
-  if (r == AFQ_OK) {
-    const hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, hipGetErrorString(e));
+  if (!tmp.empty()) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(tmp);
   }
-  free_all(tmp);
   return r;
 } catch (...) {
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
@@ -830,28 +851,24 @@ afq_status afq_force_bias_adjoint(afq_ctx* ctx, int32_t sys_id, const double* d_
   if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
   if (!d_ell || !grad_L) return fail(ctx, AFQ_EINVAL, "null pointer");
   HIPCHK(hipSetDevice(ctx->device));
-  const size_t M = s.M, N = s.N, W = s.W, G = s.G;
-  size_t gchunk = (size_t)(256ull << 20) / (N * M * 8);
-  if (gchunk < 1) gchunk = 1;
-  if (gchunk > G) gchunk = G;
+  const size_t M = s.M, W = s.W, G = s.G;
+  double *TH, *Ub, *Db, *Y, *ellt, *dl;
+  TRY(ensure_adjoint(ctx, s, &TH, &Ub, &Db, &Y, &ellt, &dl));
   std::vector<void*> tmp;
-  double *TH, *Z, *dl, *gL = grad_L;
+  double* gL = grad_L;
   afq_status r = AFQ_OK;
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &TH, W * 2 * N * M);
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &Z, gchunk * N * M);
-  if (r == AFQ_OK) r = dalloc(ctx, tmp, &dl, W * G * 2);
-  if (r == AFQ_OK && !ptr_is_device) r = dalloc(ctx, tmp, &gL, G * M * M);
+  if (!ptr_is_device) r = dalloc(ctx, tmp, &gL, G * M * M);
   if (r == AFQ_OK) r = copy_in(ctx, dl, d_ell, W * G * 2, ptr_is_device);
   if (r == AFQ_OK) {
-    const hipError_t e = launch_fb_adjoint_into(s, dl, gL, TH, Z, (int)gchunk, ctx->stream);
+    // Z of a chunk reuses Db (gchunk N M doubles)
+    const hipError_t e = launch_fb_adjoint_into(s, dl, gL, TH, Db, s.adj_gchunk, ctx->stream);
     if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, std::string("adjoint: ") + hipGetErrorString(e));
   }
   if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, grad_L, gL, G * M * M * 8, 0);
-  if (r == AFQ_OK) {
-    const hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, hipGetErrorString(e));
+  if (!tmp.empty()) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(tmp);
   }
-  free_all(tmp);
   return r;
 } catch (...) {
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");

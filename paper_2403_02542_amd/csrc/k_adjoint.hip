@@ -12,7 +12,9 @@
 // stacked rows TH[(w, plane, j)][q] = th_plane[w][j][q] and
 //   U_g[i][(w, re, j)] = d_w ( Re ell_g^w delta_ij - Re T_g^w[j][i]),
 //   U_g[i][(w, im, j)] = d_w (-Im ell_g^w delta_ij + Im T_g^w[j][i]).
-// All T_g^w of a chunk of Cholesky blocks come from one GEMM C = (Psi_T^T L) TH^T.
+// All T_g^w of a chunk of Cholesky blocks come from one product of TH with the
+// half-rotated blocks Psi_T^T L_g, written out directly as U; ell_g^w comes
+// from one product over K = (i, p).
 #include "afq_device.h"
 #include "afq_internal.h"
 
@@ -29,38 +31,74 @@ __global__ void k_stack_theta(const double* __restrict__ re, const double* __res
   TH[e] = r < NM ? re[w * NM + r] : im[w * NM + (r - NM)];
 }
 
-// U rows (g, i) of the chunk from C rows (g, j): U[(g,i)][(w,pl,j)] as above.
-__global__ void k_adj_u(int gn, int N, int W, int G1, int g0, const double* __restrict__ C,
-                        const double* __restrict__ dE, const double* __restrict__ ell_re,
-                        const double* __restrict__ ell_im, double* __restrict__ U) {
-  const int64_t cols = (int64_t)W * 2 * N;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)gn * N * cols) return;
-  const int64_t row = e / cols;
-  const int64_t col = e - row * cols;
-  const int g = (int)(row / N), i = (int)(row % N);
-  const int w = (int)(col / (2 * N));
-  const int rem = (int)(col % (2 * N));
-  const int pl = rem >= N, j = pl ? rem - N : rem;
-  // T_g^w[j][i] (plane pl) = C[(g, j)][(w, pl, i)]
-  const double t = C[((int64_t)g * N + j) * cols + (int64_t)w * 2 * N + pl * N + i];
-  const int64_t o = (int64_t)w * G1 + g0 + g;
-  double v;
-  if (!pl) v = (i == j ? ell_re[o] : 0.0) - t;
-  else v = (i == j ? -ell_im[o] : 0.0) + t;
-  U[e] = dE[w] * v;
+// U of a chunk of Cholesky blocks straight from the contraction that forms
+// T_g^w: rows r = (w, pl, i) of TH against rows c = (g, j) of the half-rotated
+// blocks give T_g^w[j][i] (plane pl) = sum_p Lx[(g, j)][p] th_pl[w][i][p],
+// stored at U[(g, i)][(w, pl, j)] (consecutive j contiguous) with the Coulomb
+// term on the diagonal and the walker weight applied.
+using UP = Pipe<4, 2, 2, 4>;
+
+__global__ __launch_bounds__(UP::NT) void k_adj_t(int W, int N, int M, int gn, int n_ct,
+                                                  const double* __restrict__ TH,
+                                                  const double* __restrict__ Lx,
+                                                  const double* __restrict__ dE,
+                                                  const double* __restrict__ ellt,
+                                                  double* __restrict__ U) {
+  extern __shared__ double smem[];
+  const int rt = blockIdx.x / n_ct, ct = blockIdx.x % n_ct;
+  const int R = W * 2 * N, Cn = gn * N;
+  const int r0 = rt * UP::ROWS, c0 = ct * UP::COLS;
+  const int nr = min(UP::ROWS, R - r0), nc = min(UP::COLS, Cn - c0);
+  auto ga = [&](int r, int k) { return TH[(int64_t)(r0 + r) * M + k]; };
+  auto gb = [&](int c, int k) { return Lx[(int64_t)(c0 + c) * M + k]; };
+  d4_t acc[2][4];
+  const PipeSplit sp = pipe_gemm<4, 2, 2, 4, false, false>(M, nr, nc, ga, gb, smem, acc);
+  const int64_t cols = (int64_t)R;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (a >= sp.mtv || b >= sp.ntv) continue;
+      const int c = pipe_col(sp, b);
+      if (c >= nc) continue;
+      const int cc = c0 + c, g = cc / N, j = cc - g * N;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = pipe_row(sp, a, e);
+        if (r >= nr) continue;
+        const int rr = r0 + r, w = rr / (2 * N), rem = rr - w * 2 * N;
+        const int pl = rem >= N, i = rem - pl * N;
+        const double t = acc[a][b][e];
+        double v = pl ? t : -t;
+        if (i == j) {
+          const double l = ellt[(int64_t)g * 2 * W + 2 * w + pl];
+          v += pl ? -l : l;
+        }
+        U[((int64_t)g * N + i) * cols + (int64_t)w * 2 * N + pl * N + j] = dE[w] * v;
+      }
+    }
 }
 
 inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+// Slices of the D contraction: enough (tiles x slices >= ~1024 workgroups)
+// to fill 256 compute units, each slice at least 512 long, S dividing 2 W N.
+int adjoint_nsplit(int M, int N, int W, int gchunk) {
+  const int64_t cols = (int64_t)W * 2 * N;
+  const int64_t tiles = (((int64_t)gchunk * N + 127) / 128) * ((M + 127) / 128);
+  int S = 1;
+  while (S < 16 && tiles * S < 1024 && cols % (2 * S) == 0 && cols / (2 * S) >= 512) S *= 2;
+  return S;
+}
+
 // grad_h and grad_L (device pointers, M x M and G x M x M).  dE on device.
 // Uses s.ell_* of the current walkers (filled by the caller).
 hipError_t launch_adjoint_into(SysDev& s, const double* dE, double* grad_h, double* grad_L,
-                               double* TH, double* Cb, double* Ub, double* Db, double* Y,
+                               double* TH, double* Ub, double* Db, double* Y, double* ellt,
                                int gchunk, hipStream_t st) {
-  const int M = s.M, N = s.N, W = s.W, G = s.G, G1 = G + 1;
+  const int M = s.M, N = s.N, W = s.W, G = s.G;
   const int NM = N * M;
   const int64_t cols = (int64_t)W * 2 * N;
   hipLaunchKernelGGL(k_stack_theta, dim3(nb((int64_t)W * 2 * NM)), dim3(256), 0, st, s.th_re,
@@ -81,32 +119,47 @@ hipError_t launch_adjoint_into(SysDev& s, const double* dE, double* grad_h, doub
   gh.C = grad_h; gh.sCb = 0; gh.sCr = M; gh.sCc = 1;
   gh.R = M; gh.Cn = M; gh.K = N; gh.kin = N; gh.batch = 1; gh.alpha = 2.0; gh.beta = 0.0;
   if ((e = launch_gemm(gh, st)) != hipSuccess) return e;
+  // Coulomb vector of every (g, walker, plane): ellt[g][(w, pl)] = 2 tr T_g^w
+  GemmArgs el{};
+  el.A = s.Lx; el.sAb = 0; el.sAr = NM; el.sAk = 1; el.sAkb = 0;
+  el.B = TH; el.sBb = 0; el.sBc = NM; el.sBk = 1; el.sBkb = 0;
+  el.C = ellt; el.sCb = 0; el.sCr = 2 * (int64_t)W; el.sCc = 1;
+  el.R = G; el.Cn = 2 * W; el.K = NM; el.kin = NM; el.batch = 1; el.alpha = 2.0; el.beta = 0.0;
+  if ((e = launch_gemm(el, st)) != hipSuccess) return e;
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    e = hipFuncSetAttribute((const void*)k_adj_t, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)UP::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
+  const int S = adjoint_nsplit(M, N, W, gchunk);
+  const int64_t kc = cols / S;
+  const int64_t dstride = (int64_t)gchunk * NM;
   for (int g0 = 0; g0 < G; g0 += gchunk) {
     const int gn = G - g0 < gchunk ? G - g0 : gchunk;
-    // C[(g, i)][(w, pl, j)] = sum_p Lx[(g0 + g, i)][p] TH[(w, pl, j)][p]
-    GemmArgs c{};
-    c.A = s.Lx + (int64_t)g0 * NM; c.sAb = 0; c.sAr = M; c.sAk = 1; c.sAkb = 0;
-    c.B = TH; c.sBb = 0; c.sBc = M; c.sBk = 1; c.sBkb = 0;
-    c.C = Cb; c.sCb = 0; c.sCr = cols; c.sCc = 1;
-    c.R = gn * N; c.Cn = (int)cols; c.K = M; c.kin = M; c.batch = 1; c.alpha = 1.0; c.beta = 0.0;
-    if ((e = launch_gemm(c, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_u, dim3(nb((int64_t)gn * N * cols)), dim3(256), 0, st, gn, N, W, G1,
-                       g0, Cb, dE, s.ell_re, s.ell_im, Ub);
+    const int n_rt = (int)((cols + UP::ROWS - 1) / UP::ROWS);
+    const int n_ct = (gn * N + UP::COLS - 1) / UP::COLS;
+    hipLaunchKernelGGL(k_adj_t, dim3(n_rt * n_ct), dim3(UP::NT), UP::LDS_BYTES, st, W, N, M, gn,
+                       n_ct, TH, s.Lx + (int64_t)g0 * NM, dE, ellt + (int64_t)g0 * 2 * W, Ub);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // D[(g, i)][q] = sum_{(w,pl,j)} U[(g, i)][(w,pl,j)] TH[(w,pl,j)][q]
+    // D = U TH: the long contraction over (w, pl, j) is cut into S equal
+    // slices (one batch entry each, partial sums D_s[(g, i)][q]) so that the
+    // few output tiles still fill the chip; the slices are summed in the next
+    // product, deterministically.
     GemmArgs d{};
-    d.A = Ub; d.sAb = 0; d.sAr = cols; d.sAk = 1; d.sAkb = 0;
-    d.B = TH; d.sBb = 0; d.sBc = 1; d.sBk = M; d.sBkb = 0;
-    d.C = Db; d.sCb = 0; d.sCr = M; d.sCc = 1;
-    d.R = gn * N; d.Cn = M; d.K = (int)cols; d.kin = (int)cols; d.batch = 1; d.alpha = 1.0;
+    d.A = Ub; d.sAb = kc; d.sAr = cols; d.sAk = 1; d.sAkb = 0;
+    d.B = TH; d.sBb = kc * M; d.sBc = 1; d.sBk = M; d.sBkb = 0;
+    d.C = Db; d.sCb = dstride; d.sCr = M; d.sCc = 1;
+    d.R = gn * N; d.Cn = M; d.K = (int)kc; d.kin = (int)kc; d.batch = S; d.alpha = 1.0;
     d.beta = 0.0;
     if ((e = launch_gemm(d, st)) != hipSuccess) return e;
-    // grad_L[g0 + g][p][q] = 2 sum_i psit[i][p] D[(g, i)][q]
+    // grad_L[g0 + g][p][q] = 2 sum_{s, i} psit[i][p] D_s[(g, i)][q]
     GemmArgs gl{};
     gl.A = s.psit; gl.sAb = 0; gl.sAr = 1; gl.sAk = M; gl.sAkb = 0;
-    gl.B = Db; gl.sBb = NM; gl.sBc = 1; gl.sBk = M; gl.sBkb = 0;
+    gl.B = Db; gl.sBb = NM; gl.sBc = 1; gl.sBk = M; gl.sBkb = dstride;
     gl.C = grad_L + (int64_t)g0 * M * M; gl.sCb = (int64_t)M * M; gl.sCr = M; gl.sCc = 1;
-    gl.R = M; gl.Cn = M; gl.K = N; gl.kin = N; gl.batch = gn; gl.alpha = 2.0; gl.beta = 0.0;
+    gl.R = M; gl.Cn = M; gl.K = N * S; gl.kin = N; gl.batch = gn; gl.alpha = 2.0; gl.beta = 0.0;
     if ((e = launch_gemm(gl, st)) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -73,6 +73,49 @@ __global__ __launch_bounds__(256) void k_gemm_generic(GemmArgs g) {
     }
 }
 
+// Same strided contraction on the pipelined engine (128 x 128 tiles of 8
+// waves) for the large set-up and adjoint products.  KB: K is a sequence of
+// blocks of kin elements (stride sAkb / sBkb between blocks).
+using GPP = Pipe<4, 2, 2, 4>;
+
+template <bool AKM, bool BKM, bool KB>
+__global__ __launch_bounds__(GPP::NT) void k_gemm_pipe(GemmArgs g, int nct) {
+  extern __shared__ double smem[];
+  const int rt = blockIdx.x / nct, ct = blockIdx.x % nct;
+  const int64_t b = blockIdx.y;
+  const int r0 = rt * GPP::ROWS, c0 = ct * GPP::COLS;
+  const int nr = min(GPP::ROWS, g.R - r0), nc = min(GPP::COLS, g.Cn - c0);
+  const double* A = g.A + b * g.sAb + (int64_t)r0 * g.sAr;
+  const double* B = g.B + b * g.sBb + (int64_t)c0 * g.sBc;
+  auto koff = [&](int k, int64_t sk, int64_t skb) {
+    if (!KB) return (int64_t)k * sk;
+    const int kb = k / g.kin;
+    return (int64_t)kb * skb + (int64_t)(k - kb * g.kin) * sk;
+  };
+  auto ga = [&](int r, int k) { return A[(int64_t)r * g.sAr + koff(k, g.sAk, g.sAkb)]; };
+  auto gb = [&](int c, int k) { return B[(int64_t)c * g.sBc + koff(k, g.sBk, g.sBkb)]; };
+  d4_t acc[2][4];
+  const PipeSplit sp = pipe_gemm<4, 2, 2, 4, AKM, BKM>(g.K, nr, nc, ga, gb, smem, acc);
+  double* C = g.C + b * g.sCb;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (i >= sp.mtv || j >= sp.ntv) continue;
+      const int c = pipe_col(sp, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = pipe_row(sp, i, e);
+        if (r < nr && c < nc) {
+          const int64_t idx = (int64_t)(r0 + r) * g.sCr + (int64_t)(c0 + c) * g.sCc;
+          double v = g.alpha * acc[i][j][e];
+          if (g.beta != 0.0) v += g.beta * C[idx];
+          C[idx] = v;
+        }
+      }
+    }
+}
+
 // ------------------------------------------------------------ one-body step
 // out[(plane, w, j)][p] = sum_q in[(plane, w, j)][q] B[p][q]   (B symmetric)
 
@@ -492,7 +535,36 @@ __global__ __launch_bounds__(256) void k_krylov_combine(int WN, int M, int kmax,
 
 // ==================================================================== launchers
 
+template <bool AKM, bool BKM, bool KB>
+hipError_t run_gemm_pipe(const GemmArgs& g, hipStream_t st) {
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_gemm_pipe<AKM, BKM, KB>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)GPP::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
+  const int nrt = (g.R + GPP::ROWS - 1) / GPP::ROWS;
+  const int nct = (g.Cn + GPP::COLS - 1) / GPP::COLS;
+  hipLaunchKernelGGL((k_gemm_pipe<AKM, BKM, KB>), dim3(nrt * nct, g.batch), dim3(GPP::NT),
+                     GPP::LDS_BYTES, st, g, nct);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
+  if (g.R <= 0 || g.Cn <= 0 || g.batch <= 0) return hipSuccess;
+  // Large products go to the pipelined engine; small ones (a few tiles) to
+  // the plain kernel, whose 64 x 64 tiles waste less on ragged edges.
+  if ((double)g.R * g.Cn * g.K * g.batch >= (double)(1 << 24) && g.R >= 64 && g.Cn >= 64) {
+    const bool akm = g.sAk != 1, bkm = g.sBk != 1, kb = g.kin < g.K;
+    if (akm) {
+      if (bkm) return kb ? run_gemm_pipe<true, true, true>(g, st) : run_gemm_pipe<true, true, false>(g, st);
+      return kb ? run_gemm_pipe<true, false, true>(g, st) : run_gemm_pipe<true, false, false>(g, st);
+    }
+    if (bkm) return kb ? run_gemm_pipe<false, true, true>(g, st) : run_gemm_pipe<false, true, false>(g, st);
+    return kb ? run_gemm_pipe<false, false, true>(g, st) : run_gemm_pipe<false, false, false>(g, st);
+  }
   constexpr int MT = 2, NT = 2;
   const int nrt = (g.R + 32 * MT - 1) / (32 * MT);
   const int nct = (g.Cn + 32 * NT - 1) / (32 * NT);
