@@ -13,12 +13,15 @@ symmetric real L_g for every Cholesky index g (so that
 and an orthonormal real trial with N doubly occupied orbitals.
 """
 from .generate import (  # noqa: F401
+    C4,
     CONFIGS,
     Hamiltonian,
+    UnevenBatch,
     WorkloadConfig,
     fields,
     hamiltonian,
     make_system,
+    make_uneven_batch,
     rhf_trial,
     uneven_batch_sizes,
 )

@@ -142,6 +142,45 @@ def make_system(cfg: WorkloadConfig, trial_iters: int = 10):
     return ham, psi
 
 
+@dataclasses.dataclass(frozen=True)
+class UnevenBatch:
+    """Many systems of uneven size propagated together: M ~ U{m_lo..m_hi},
+    N = M // 6, G = 5 M, the same walker count, time step and Krylov
+    dimension for all; system i uses seed i, scaled sigmas (1 / sqrt(M))
+    and a trial from `trial_iters` Roothaan iterations."""
+    name: str
+    n_sys: int
+    W: int
+    tau: float
+    k: int
+    steps: int
+    reorth_every: int
+    m_lo: int = 40
+    m_hi: int = 400
+    seed: int = 0
+    trial_iters: int = 3
+
+    def configs(self):
+        return [_cfg(f"{self.name}[{i}]", M, N, G, self.W, self.tau, self.k, self.steps,
+                     self.reorth_every, scaled=True, seed=i)
+                for i, (M, N, G) in enumerate(
+                    uneven_batch_sizes(self.n_sys, self.m_lo, self.m_hi, self.seed))]
+
+
+C4 = UnevenBatch("c4", n_sys=48, W=64, tau=0.05, k=8, steps=20, reorth_every=1)
+
+
+def make_uneven_batch(batch: UnevenBatch, only=None):
+    """[(config, Hamiltonian, trial)] of the batch (or of the listed systems)."""
+    out = []
+    for i, cfg in enumerate(batch.configs()):
+        if only is not None and i not in only:
+            continue
+        ham, psi = make_system(cfg, trial_iters=batch.trial_iters)
+        out.append((cfg, ham, psi))
+    return out
+
+
 def uneven_batch_sizes(n_sys: int = 48, m_lo: int = 40, m_hi: int = 400,
                        seed: int = 0):
     """Orbital counts of the uneven multi-system batch: M ~ U{m_lo..m_hi},

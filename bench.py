@@ -180,6 +180,158 @@ def adjoint_bench(args):
     print(json.dumps(out))
 
 
+def _oracle_system_worker(cfg):
+    """One walker-step of the oracle on one system of the uneven batch (after
+    one warm-up step); the system is generated inside the worker."""
+    from threadpoolctl import threadpool_limits
+    from oracle import afq_oracle as O
+    with threadpool_limits(1):
+        ham, psi = W.make_system(cfg, trial_iters=W.C4.trial_iters)
+        p = O.prepare(ham.h, ham.L, ham.e_core, psi, cfg.tau)
+        wk = O.init_walker(p)
+        wk, _ = O.walker_step(p, wk, W.fields(0, 0, 0, cfg.W, cfg.G)[0], O.EXP_KRYLOV, cfg.k,
+                              O.reorth_due(0, cfg.reorth_every))
+        t0 = time.perf_counter()
+        O.walker_step(p, wk, W.fields(0, 0, 1, cfg.W, cfg.G)[0], O.EXP_KRYLOV, cfg.k,
+                      O.reorth_due(1, cfg.reorth_every))
+        return cfg.M, time.perf_counter() - t0
+
+
+def uneven_cpu_baseline(cfgs, nproc):
+    """Oracle walker-step times on systems at six size quantiles, log-log
+    interpolated over all systems of the batch."""
+    import multiprocessing as mp
+    order = sorted(range(len(cfgs)), key=lambda i: cfgs[i].M)
+    pick = sorted({order[int(round(q * (len(order) - 1)))] for q in np.linspace(0, 1, 6)})
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(nproc, len(pick))) as pool:
+        res = sorted(pool.map(_oracle_system_worker, [cfgs[i] for i in pick]))
+    wall = time.perf_counter() - t0
+    lm = np.log([m for m, _ in res])
+    lt = np.log([t for _, t in res])
+    per_step = sum(c.W * math.exp(np.interp(math.log(c.M), lm, lt)) for c in cfgs)
+    rate = sum(c.W for c in cfgs) / per_step
+    return {"value": rate, "unit": "walker-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "one walker-step (after a warm-up step) of the oracle, one BLAS thread, on "
+                      f"the systems with M = {[m for m, _ in res]} "
+                      f"(s per walker-step: {[round(t, 3) for _, t in res]}); the batch's step "
+                      "time is the sum over all systems and walkers of the log-log interpolated "
+                      f"per-walker time ({per_step:.0f} s per batch step on one core); "
+                      f"wall {wall:.1f} s"}
+
+
+def uneven_bench(args):
+    """Throughput of the 48-system uneven batch (M ~ U{40..400}, N = M/6,
+    G = 5M, 64 walkers each, Krylov k = 8, tau = 0.05, QR every step)."""
+    import torch
+    from paper_2403_02542_amd import afq
+    batch = W.C4
+    cfgs = batch.configs()
+    cpu = None
+    if not args.no_cpu:
+        nproc = args.cpu_procs or max(1, min(16, len(os.sched_getaffinity(0))))
+        log("CPU oracle baseline on sampled systems")
+        cpu = uneven_cpu_baseline(cfgs, nproc)
+        log(f"CPU oracle: {cpu['value']:.3f} walker-steps/s")
+    log("initialising the GPU library")
+    ctx = afq.Context(0)
+    ids = []
+    for i, cfg in enumerate(cfgs):
+        ham, psi = W.make_system(cfg, trial_iters=batch.trial_iters)
+        sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+        ctx.init_trial(sid, psi)
+        ctx.init_walkers(sid, batch.W)
+        ids.append(sid)
+        del ham
+        log(f"system {i + 1}/{len(cfgs)}: M={cfg.M} N={cfg.N} G={cfg.G}")
+    sched = {"auto": afq.SCHED_AUTO, "serial": afq.SCHED_SERIAL, "streams": afq.SCHED_STREAMS,
+             "graph": afq.SCHED_GRAPH}[args.schedule]
+    kw = dict(tau=batch.tau, exp_method=afq.EXP_KRYLOV, exp_order=batch.k,
+              reorth_every=batch.reorth_every, seed=0, schedule=sched)
+    if args.autotune:
+        log("autotuning tiles")
+        ctx.autotune(ids, **{k: v for k, v in kw.items() if k != "schedule"})
+    warm = args.warmup + (args.warmup % 2)   # even: the graph's buffer state repeats
+    energies = torch.zeros((len(ids), args.steps, 2), dtype=torch.float64, device="cuda")
+    ew = torch.zeros((len(ids), max(1, warm), 2), dtype=torch.float64, device="cuda")
+    step0 = 0
+
+    def timed(schedule):
+        nonlocal step0
+        k = dict(kw, schedule=schedule)
+        log(f"schedule {schedule}: warm-up {warm} steps")
+        ctx.propagate_batch(ids, n_steps=warm, step0=step0, energies_out=ew, **k)
+        ctx.sync()
+        torch.cuda.synchronize()
+        log(f"schedule {schedule}: timed {args.steps} steps")
+        t0 = time.perf_counter()
+        ctx.propagate_batch(ids, n_steps=args.steps, step0=step0 + warm, energies_out=energies,
+                            **k)
+        ctx.sync()
+        torch.cuda.synchronize()
+        step0 += warm + args.steps
+        return time.perf_counter() - t0
+
+    compare = {}
+    if args.compare_schedules:
+        for name in ("serial", "streams", "graph"):
+            if name != args.schedule:
+                dtn = timed({"serial": afq.SCHED_SERIAL, "streams": afq.SCHED_STREAMS,
+                             "graph": afq.SCHED_GRAPH}[name])
+                compare[name] = {"ms_per_step": dtn / args.steps * 1e3,
+                                 "walker_steps_per_s": len(ids) * batch.W * args.steps / dtn}
+    dt = timed(sched)
+    n_ws = len(ids) * batch.W
+    value = n_ws * args.steps / dt
+    # per-size breakdown: every system alone, one step after the other
+    log("per-system steps alone")
+    per = []
+    kw1 = dict(kw, schedule=afq.SCHED_SERIAL)
+    for i, sid in enumerate(ids):
+        ctx.sync()
+        t1 = time.perf_counter()
+        ctx.propagate_batch(sid, n_steps=2, step0=step0, **kw1)
+        ctx.sync()
+        ms = (time.perf_counter() - t1) / 2 * 1e3
+        per.append({"M": cfgs[i].M, "N": cfgs[i].N, "G": cfgs[i].G, "ms_per_step_alone": ms,
+                    "walker_steps_per_s_alone": batch.W / ms * 1e3})
+    step0 += 2
+    # phases (one step after the other, HIP events) for the local-energy roofline
+    ctx.profile(True)
+    ctx.profile_read()
+    ctx.propagate_batch(ids, n_steps=2, step0=step0, **kw1)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ex_ms, ex_n = prof["exchange"]
+    ex_fl = 2 * sum(exchange_flops_per_walker(c.M, c.N, c.G) * c.W for c in cfgs)
+    achieved = ex_fl / (ex_ms / 1e3) if ex_ms > 0 else 0.0
+    alone_ms = sum(p["ms_per_step_alone"] for p in per)
+    out = {
+        "metric": "walker-steps/sec over 48 uneven systems (M ~ U{40..400}, FP64)",
+        "value": value, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": warm, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (48 seeded random Cholesky Hamiltonians, mean-field trials, Philox "
+                "fields)",
+        "config": {"workload": f"c4: {len(ids)} systems, M ~ U{{40..400}}, N = M//6, G = 5M, "
+                               f"{batch.W} walkers each, Krylov k={batch.k}, tau={batch.tau}, "
+                               f"QR every {batch.reorth_every}",
+                   "schedule": args.schedule, "autotune": bool(args.autotune),
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "kernel": "k_exchange (per system, one after the other, HIP events)",
+                     "exchange_ms_per_step": ex_ms / 2},
+        "sum_alone_ms_per_step": alone_ms,
+        "batched_speedup_vs_alone": alone_ms / (dt / args.steps * 1e3),
+        "other_schedules": compare,
+        "per_size": per,
+        "phases_serial_ms_per_step": {k: v[0] / 2 for k, v in prof.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 _CPU_STATE = {}
 _T0 = time.perf_counter()
 
@@ -248,9 +400,18 @@ def main():
                          "HBM byte counters of a profiler) and exit")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the adjoint entry points at the c5 shape instead of the step")
+    ap.add_argument("--uneven", action="store_true",
+                    help="time the 48-system uneven batch (c4) instead of the single system")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "streams", "graph"])
+    ap.add_argument("--autotune", action="store_true", help="tune tile shapes before timing")
+    ap.add_argument("--compare-schedules", action="store_true",
+                    help="with --uneven: also time the other schedules")
     args = ap.parse_args()
     if args.adjoint and args.gpus == 1:
         adjoint_bench(args)
+        return
+    if args.uneven and args.gpus == 1:
+        uneven_bench(args)
         return
     if args.copy_probe:
         import torch

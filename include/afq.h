@@ -101,7 +101,24 @@ typedef struct {
                             fields (single-system calls only); NULL = Philox     */
   double* energies_out;  /* optional DEVICE array [n_sys][n_steps][2]:
                             (sum_w W E_L capped, sum_w W) per step               */
+  int32_t schedule;      /* AFQ_SCHED_*: how the steps of several systems are
+                            issued (results are the same for every schedule)     */
 } afq_prop_params;
+
+/* Schedules of afq_propagate_batch.
+ *  SERIAL:  system after system, phase after phase, on the context stream.
+ *  STREAMS: per step, the per-system work up to the new Green's function runs
+ *           on four branch streams (systems assigned longest-first), then one
+ *           local-energy launch per kernel instance covers all systems (FP64;
+ *           tiles ordered longest-first), then the energies.
+ *  GRAPH:   STREAMS captured once as a two-step HIP graph and replayed (the
+ *           step index, reorthonormalisation schedule and estimator slot are
+ *           read from device memory).  Krylov exponential only.
+ *  AUTO:    SERIAL for one system; GRAPH (Krylov) or STREAMS (Taylor) for
+ *           several.  STREAMS and GRAPH need library fields (fields == NULL),
+ *           energy_every <= 1 and profiling off (EINVAL otherwise); AUTO then
+ *           falls back to SERIAL. */
+enum { AFQ_SCHED_AUTO = 0, AFQ_SCHED_SERIAL = 1, AFQ_SCHED_STREAMS = 2, AFQ_SCHED_GRAPH = 3 };
 
 /* Run n_steps Split-2 walker steps on every walker of the listed systems.
  * Per step and walker (Sec. II.A, III.B, IV, V): force bias from the current

@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libafq.so"
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = range(6)
 EXP_KRYLOV, EXP_TAYLOR = 0, 1
 PREC_FP64, PREC_MIXED, PREC_MIXED_FAST = 0, 1, 2
+SCHED_AUTO, SCHED_SERIAL, SCHED_STREAMS, SCHED_GRAPH = 0, 1, 2, 3
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENUMERIC"}
 
 EXPORTED = (
@@ -52,6 +53,7 @@ class PropParams(ctypes.Structure):
         ("step0", ctypes.c_uint64),
         ("fields", ctypes.c_void_p),
         ("energies_out", ctypes.c_void_p),
+        ("schedule", ctypes.c_int32),
     ]
 
 
@@ -178,7 +180,7 @@ class Context:
     # --------------------------------------------------------------- stepping
     def propagate_batch(self, sys_ids, *, tau, n_steps, exp_method=EXP_KRYLOV, exp_order=6,
                         reorth_every=1, precision=PREC_FP64, energy_every=1, e0=None, seed=0,
-                        step0=0, fields=None, energies_out=None):
+                        step0=0, fields=None, energies_out=None, schedule=SCHED_AUTO):
         ids = [sys_ids] if isinstance(sys_ids, int) else list(sys_ids)
         arr = (ctypes.c_int32 * len(ids))(*ids)
         fp, fdev, fk = _arg(fields, np.float64)
@@ -189,7 +191,8 @@ class Context:
             raise ValueError("energies_out must be a device tensor")
         prm = PropParams(float(tau), int(exp_method), int(exp_order), int(reorth_every),
                          int(precision), int(n_steps), int(energy_every),
-                         math.nan if e0 is None else float(e0), int(seed), int(step0), fp, ep)
+                         math.nan if e0 is None else float(e0), int(seed), int(step0), fp, ep,
+                         int(schedule))
         self._check(self._lib.afq_propagate_batch(self._h, arr, len(ids), ctypes.byref(prm)))
 
     def local_energy_batch(self, sys_id: int, eloc_out=None, ell_out=None, precision=PREC_FP64):

@@ -64,11 +64,38 @@ struct SysDev {
   int64_t Lxb_ps = 0;
   unsigned short* thb = nullptr;  // [P][W 2N][Kp] pieces of Theta
   int64_t thb_ps = 0;
+  // tuned tile shape of the local-energy contraction (0 = occupancy model)
+  int x_ga = 0, x_wb = 0;
+  // tuned column blocks of the operator-orbital product (0 = default)
+  int mv_ct = 0;
   // adjoint workspace (allocated on first use, sized for the walker count)
   double* adj_ws = nullptr;
   size_t adj_ws_n = 0;        // doubles
   int adj_gchunk = 0;         // Cholesky blocks per chunk of the adjoint
   std::vector<void*> walker_allocs;
+};
+
+// Step state of a propagate call held in device memory, so that captured
+// launches stay valid across replays: the fields, the reorthonormalisation
+// schedule and the estimator slot read the current step from here.
+struct CallState {
+  uint64_t step;       // global index of the step that runs next (advanced per replay)
+  uint64_t step0;      // first step of the call
+  int64_t n_steps;     // steps of the call (row length of the estimator output)
+  double* energies;    // [n_sys][n_steps][2] estimator output, or null
+};
+
+// One system's operands of the local-energy contraction (also one entry of
+// a many-system launch).  ct: column tiles of its kernel instance.
+struct XSys {
+  const double* Lx;
+  const double* th_re;
+  const double* th_im;
+  double* ell_re;
+  double* ell_im;
+  double* ex_re;
+  double* ex_im;
+  int G1, N, M, W, GA, WB, grp, ct;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -88,7 +115,10 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 
 hipError_t launch_fields(uint64_t seed, uint64_t sid, uint64_t step, int W, int G, double* out,
-                         hipStream_t st);
+                         hipStream_t st, const CallState* cs = nullptr, int add = 0);
+hipError_t launch_call_begin(CallState* cs, uint64_t step0, int64_t n_steps, double* energies,
+                             hipStream_t st);
+hipError_t launch_call_advance(CallState* cs, int n, hipStream_t st);
 hipError_t launch_lbar(const SysDev& s, hipStream_t st);
 hipError_t launch_axpy_L(const SysDev& s, const double* coef, double alpha, double* out,
                          hipStream_t st);
@@ -114,16 +144,34 @@ hipError_t launch_weight(SysDev& s, double tau, double e0, const double* qr_logr
                          hipStream_t st);
 // Reorthonormalisation of (ph_re, ph_im) in place; writes qr_logr[W] and
 // marks walkers whose factorisation fails in s.bad.
-hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st);
+// With cs set, the kernel itself decides from the device step whether this
+// step reorthonormalises (qr_logr = 0 when it does not).
+hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st,
+                     const CallState* cs = nullptr, int add = 0, int every = 0);
 hipError_t launch_commit(SysDev& s, hipStream_t st);
 // Local energy of W walkers with Green's functions (th_re, th_im).
 hipError_t launch_exchange(SysDev& s, int W, const double* th_re, const double* th_im,
                            double* ell_re, double* ell_im, double* ex_re, double* ex_im,
                            hipStream_t st);
+// Operands and grid of one system's contraction (tile shape from the tuner
+// when set, else from the occupancy model).
+hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const double* th_im,
+                          double* ell_re, double* ell_im, double* ex_re, double* ex_im, XSys* p,
+                          int* n_gt, int* n_wt);
+// Tiles (gt, wt) of one system in the single-system launch order.
+void exchange_tile_order(int n_gt, int n_wt, std::vector<int2>& out);
+// One launch over the tiles (system, gt, wt) of systems sharing the kernel
+// instance ct; d_sys and d_tiles are device tables.
+hipError_t launch_exchange_group(int ct, const XSys* d_sys, const int4* d_tiles, int n_tiles,
+                                 hipStream_t st);
+// Admissible (GA, WB) tile shapes for N, best first by the occupancy model.
+void exchange_candidates(int N, std::vector<int2>& out);
 hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* ell_im,
                          const double* ex_re, const double* ex_im, double* eloc, double* ecap,
                          double e0, double tau, hipStream_t st);
-hipError_t launch_estimator(SysDev& s, double* out2, hipStream_t st);
+// With cs->energies set, out2 is replaced by row `row` of that array at the device step.
+hipError_t launch_estimator(SysDev& s, double* out2, hipStream_t st, const CallState* cs = nullptr,
+                            int add = 0, int64_t row = 0);
 hipError_t launch_counters(SysDev& s, int reset, hipStream_t st);
 // Boundary layout (complex128 [W][M][N], interleaved) <-> planar [W][N][M].
 hipError_t launch_to_planar(const double* in, int W, int M, int N, double* re, double* im,

@@ -3,6 +3,7 @@
 // enqueues the kernels of one walker step after another on one HIP stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -29,6 +30,27 @@ struct afq_ctx {
   std::string err;
   std::vector<SysDev*> systems;
   std::vector<std::vector<void*>> sys_allocs;
+  // many-system schedule: branch streams (default priority), fork/join
+  // events, the device step state of graph replays, the tile tables of the
+  // many-system local-energy launches and the captured step graphs
+  static constexpr int kBranches = 4;
+  hipStream_t br[kBranches] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kBranches] = {};
+  CallState* cs = nullptr;
+  struct XTable {
+    std::vector<char> key;
+    XSys* d_sys = nullptr;
+    int4* d_tiles = nullptr;
+    std::vector<int> ct, begin, count;
+  };
+  std::vector<XTable> xtables;
+  struct GraphEntry {
+    std::vector<char> key;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+  };
+  std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -257,18 +279,26 @@ struct Phase {
   }
 };
 
+// E0 of a system for a propagate call: the call's value, or the trial energy.
+double e0_of(const SysDev& s, const afq_prop_params& P) {
+  return std::isnan(P.e0) ? s.e_trial : P.e0;
+}
+
 bool reorth_due(uint64_t t, int every) { return every > 0 && ((t + 1) % (uint64_t)every) == 0; }
 
-afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_params& P, int si,
-                       int n_sys_index, double e0) {
-  hipStream_t st = ctx->stream;
-  const uint64_t t = P.step0 + (uint64_t)si;
+// Everything of one walker step up to the new Green's function: fields,
+// force bias, operator, B exp(A) B, overlap and weight, reorthonormalisation
+// and the commit of the new state.  With cs set (captured replays) the step
+// index is read on the device, offset by `add`.
+afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_params& P,
+                      const double* x_given, uint64_t t, const CallState* cs, int add,
+                      hipStream_t st) {
   const double* x = s.x;
-  if (P.fields) {
-    x = P.fields + (size_t)si * s.W * s.G;
+  if (x_given) {
+    x = x_given;
   } else {
     Phase ph(ctx, AFQ_PH_FIELDS);
-    HIPCHK(launch_fields(P.seed, (uint64_t)sid, t, s.W, s.G, s.x, st));
+    HIPCHK(launch_fields(P.seed, (uint64_t)sid, t, s.W, s.G, s.x, st, cs, add));
   }
   {
     Phase ph(ctx, AFQ_PH_FORCE_BIAS);
@@ -298,14 +328,23 @@ afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_para
     Phase ph(ctx, AFQ_PH_OVERLAP);
     HIPCHK(launch_overlap(s, s.W, s.phn_re, s.phn_im, s.logdet_n, s.thn_re, s.thn_im, s.bad, st));
   }
-  const bool qr = reorth_due(t, P.reorth_every);
-  if (qr) {
-    Phase ph(ctx, AFQ_PH_QR);
-    HIPCHK(launch_qr(s, s.phn_re, s.phn_im, s.qr_logr, st));
+  bool qr;
+  if (cs) {
+    qr = P.reorth_every > 0;   // the kernel applies the schedule itself
+    if (qr) {
+      Phase ph(ctx, AFQ_PH_QR);
+      HIPCHK(launch_qr(s, s.phn_re, s.phn_im, s.qr_logr, st, cs, add, P.reorth_every));
+    }
+  } else {
+    qr = reorth_due(t, P.reorth_every);
+    if (qr) {
+      Phase ph(ctx, AFQ_PH_QR);
+      HIPCHK(launch_qr(s, s.phn_re, s.phn_im, s.qr_logr, st));
+    }
   }
   {
     Phase ph(ctx, AFQ_PH_WEIGHT);
-    HIPCHK(launch_weight(s, P.tau, e0, qr ? s.qr_logr : nullptr, st));
+    HIPCHK(launch_weight(s, P.tau, e0_of(s, P), qr ? s.qr_logr : nullptr, st));
   }
   {
     Phase ph(ctx, AFQ_PH_WEIGHT);
@@ -315,24 +354,269 @@ afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_para
   std::swap(s.phi_im, s.phn_im);
   std::swap(s.th_re, s.thn_re);
   std::swap(s.th_im, s.thn_im);
+  return AFQ_OK;
+}
+
+// Local-energy contraction of one system (FP64 or BF16-split).
+afq_status step_exchange(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, hipStream_t st) {
+  Phase ph(ctx, AFQ_PH_EXCHANGE);
+  if (P.precision == AFQ_PREC_FP64) {
+    HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
+  } else {
+    HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps, s.thb,
+                              st));
+    HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
+  }
+  return AFQ_OK;
+}
+
+// Energies and the weighted estimator of step si (row `row` of energies_out).
+afq_status step_energy(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, int si, int row,
+                       const CallState* cs, int add, hipStream_t st) {
+  Phase ph(ctx, AFQ_PH_ENERGY);
+  HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, e0_of(s, P),
+                       P.tau, st));
+  double* out = (!cs && P.energies_out) ? P.energies_out + ((size_t)row * P.n_steps + si) * 2
+                                        : s.est;
+  HIPCHK(launch_estimator(s, out, st, cs, add, row));
+  return AFQ_OK;
+}
+
+afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_params& P, int si,
+                       int row) {
+  const uint64_t t = P.step0 + (uint64_t)si;
+  const double* x = P.fields ? P.fields + (size_t)si * s.W * s.G : nullptr;
+  TRY(step_front(ctx, sid, s, P, x, t, nullptr, 0, ctx->stream));
   const int every = P.energy_every > 0 ? P.energy_every : 1;
-  {
-    Phase ph(ctx, AFQ_PH_EXCHANGE);
-    if (P.precision == AFQ_PREC_FP64) {
-      HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
-    } else {
-      HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps,
-                                s.thb, st));
-      HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
-                                st));
+  TRY(step_exchange(ctx, s, P, ctx->stream));
+  if ((si + 1) % every == 0 || si + 1 == P.n_steps)
+    TRY(step_energy(ctx, s, P, si, row, nullptr, 0, ctx->stream));
+  return AFQ_OK;
+}
+
+// ------------------------------------------------------------ many systems
+
+afq_status ensure_sched(afq_ctx* ctx) {
+  if (ctx->cs) return AFQ_OK;
+  for (int b = 0; b < afq_ctx::kBranches; ++b) {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->br[b], hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_join[b], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipMalloc(&ctx->cs, sizeof(CallState)));
+  return AFQ_OK;
+}
+
+// Rough cost of one step of a system (flops), for branch balancing and the
+// order of the many-system local-energy tiles.
+double step_cost(const SysDev& s, int k) {
+  const double M = s.M, N = s.N, G = s.G, W = s.W;
+  return W * ((G + 1) * 4.0 * N * N * M + 4.0 * G * M * M + 8.0 * k * M * M * N);
+}
+
+// Systems to branches: longest step first, each to the least loaded branch.
+std::vector<std::vector<int>> assign_branches(const std::vector<SysDev*>& ss, int k) {
+  const int n = (int)ss.size();
+  const int nb = n < afq_ctx::kBranches ? n : afq_ctx::kBranches;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return step_cost(*ss[a], k) > step_cost(*ss[b], k); });
+  std::vector<std::vector<int>> br(nb);
+  std::vector<double> load(nb, 0.0);
+  for (int i : order) {
+    int b = 0;
+    for (int c = 1; c < nb; ++c)
+      if (load[c] < load[b]) b = c;
+    br[b].push_back(i);
+    load[b] += step_cost(*ss[i], k);
+  }
+  return br;
+}
+
+template <class T>
+void put_bytes(std::vector<char>& key, const T& v) {
+  const char* p = reinterpret_cast<const char*>(&v);
+  key.insert(key.end(), p, p + sizeof(T));
+}
+
+// Tile table of the many-system local-energy launch for the systems' current
+// Green's-function buffers (built once per buffer state, then reused).
+afq_status get_xtable(afq_ctx* ctx, const std::vector<SysDev*>& ss, afq_ctx::XTable** out) {
+  const int n = (int)ss.size();
+  std::vector<XSys> xs(n);
+  std::vector<int> ngt(n), nwt(n);
+  std::vector<char> key;
+  for (int i = 0; i < n; ++i) {
+    SysDev& s = *ss[i];
+    const hipError_t e = exchange_setup(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re,
+                                        s.ex_im, &xs[i], &ngt[i], &nwt[i]);
+    if (e != hipSuccess) return fail(ctx, AFQ_EINVAL, "local-energy tile set-up failed");
+    put_bytes(key, xs[i]);
+  }
+  for (auto& t : ctx->xtables)
+    if (t.key == key) {
+      *out = &t;
+      return AFQ_OK;
+    }
+  afq_ctx::XTable t;
+  t.key = key;
+  std::vector<int4> tiles;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  // longest tiles first (K = M), larger systems first within equal M
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (xs[a].M != xs[b].M) return xs[a].M > xs[b].M;
+    return (int64_t)ngt[a] * nwt[a] > (int64_t)ngt[b] * nwt[b];
+  });
+  std::vector<int2> tl;
+  for (int ct : {10, 8, 7, 4}) {
+    const int begin = (int)tiles.size();
+    for (int i : order) {
+      if (xs[i].ct != ct) continue;
+      tl.clear();
+      exchange_tile_order(ngt[i], nwt[i], tl);
+      for (const int2& g : tl) tiles.push_back(int4{i, g.x, g.y, 0});
+    }
+    if ((int)tiles.size() > begin) {
+      t.ct.push_back(ct);
+      t.begin.push_back(begin);
+      t.count.push_back((int)tiles.size() - begin);
     }
   }
-  if ((si + 1) % every == 0 || si + 1 == P.n_steps) {
-    Phase ph(ctx, AFQ_PH_ENERGY);
-    HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, e0, P.tau,
-                         st));
-    double* out = P.energies_out ? P.energies_out + ((size_t)n_sys_index * P.n_steps + si) * 2 : s.est;
-    HIPCHK(launch_estimator(s, out, st));
+  std::vector<void*> tmp;
+  TRY(dalloc(ctx, tmp, &t.d_sys, (size_t)n));
+  afq_status r = dalloc(ctx, tmp, &t.d_tiles, tiles.size());
+  if (r != AFQ_OK) {
+    free_all(tmp);
+    return r;
+  }
+  hipError_t e = hipMemcpy(t.d_sys, xs.data(), sizeof(XSys) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(t.d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_all(tmp);
+    return fail(ctx, AFQ_EDEVICE, std::string("tile table: ") + hipGetErrorString(e));
+  }
+  if (ctx->xtables.size() >= 16) {   // bound the cache; tables in use are waited for
+    HIPCHK(hipDeviceSynchronize());
+    for (auto& o : ctx->xtables) {
+      (void)hipFree(o.d_sys);
+      (void)hipFree(o.d_tiles);
+    }
+    ctx->xtables.clear();
+  }
+  ctx->xtables.push_back(std::move(t));
+  *out = &ctx->xtables.back();
+  return AFQ_OK;
+}
+
+// One step of several systems: the per-system front halves run on the branch
+// streams, then (FP64) one local-energy launch per kernel instance covers all
+// systems, then the energies.  Host step t / row index si are used when cs
+// is null; under capture the device step state is read instead.
+afq_status batch_step(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*>& ss,
+                      const std::vector<std::vector<int>>& branches, const afq_prop_params& P,
+                      uint64_t t, int si, const CallState* cs, int add) {
+  hipStream_t origin = ctx->stream;
+  const int nb = (int)branches.size();
+  HIPCHK(hipEventRecord(ctx->ev_fork, origin));
+  for (int b = 0; b < nb; ++b) HIPCHK(hipStreamWaitEvent(ctx->br[b], ctx->ev_fork, 0));
+  for (int b = 0; b < nb; ++b)
+    for (int i : branches[b]) TRY(step_front(ctx, ids[i], *ss[i], P, nullptr, t, cs, add, ctx->br[b]));
+  for (int b = 0; b < nb; ++b) {
+    HIPCHK(hipEventRecord(ctx->ev_join[b], ctx->br[b]));
+    HIPCHK(hipStreamWaitEvent(origin, ctx->ev_join[b], 0));
+  }
+  if (P.precision == AFQ_PREC_FP64) {
+    afq_ctx::XTable* tab;
+    TRY(get_xtable(ctx, ss, &tab));
+    for (size_t c = 0; c < tab->ct.size(); ++c)
+      HIPCHK(launch_exchange_group(tab->ct[c], tab->d_sys, tab->d_tiles + tab->begin[c],
+                                   tab->count[c], origin));
+  } else {
+    for (SysDev* s : ss) TRY(step_exchange(ctx, *s, P, origin));
+  }
+  for (int i = 0; i < (int)ss.size(); ++i) TRY(step_energy(ctx, *ss[i], P, si, i, cs, add, origin));
+  return AFQ_OK;
+}
+
+// Steps of several systems as replays of a captured two-step graph (the
+// buffer swaps of two steps cancel, so the captured pointers stay valid).
+afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*>& ss,
+                     const std::vector<std::vector<int>>& branches, const afq_prop_params& P) {
+  const int n = (int)ss.size();
+  std::vector<char> key;
+  for (int i = 0; i < n; ++i) {
+    put_bytes(key, ids[i]);
+    put_bytes(key, ss[i]->th_re);
+    put_bytes(key, ss[i]->phi_re);
+    put_bytes(key, e0_of(*ss[i], P));
+  }
+  put_bytes(key, P.tau);
+  put_bytes(key, P.exp_method);
+  put_bytes(key, P.exp_order);
+  put_bytes(key, P.reorth_every);
+  put_bytes(key, P.precision);
+  put_bytes(key, P.seed);
+  afq_ctx::GraphEntry* ge = nullptr;
+  for (auto& g : ctx->graphs)
+    if (g.key == key) ge = &g;
+  hipStream_t origin = ctx->stream;
+  if (!ge) {
+    // tile tables of both buffer states first (no allocation under capture)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (SysDev* s : ss) {
+        std::swap(s->th_re, s->thn_re);
+        std::swap(s->th_im, s->thn_im);
+      }
+      if (P.precision == AFQ_PREC_FP64) {
+        afq_ctx::XTable* tab;
+        afq_status r = get_xtable(ctx, ss, &tab);
+        if (r != AFQ_OK) {
+          if (pass == 0)
+            for (SysDev* s : ss) {
+              std::swap(s->th_re, s->thn_re);
+              std::swap(s->th_im, s->thn_im);
+            }
+          return r;
+        }
+      }
+    }
+    afq_ctx::GraphEntry g;
+    g.key = key;
+    HIPCHK(hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed));
+    afq_status r = batch_step(ctx, ids, ss, branches, P, 0, 0, ctx->cs, 0);
+    if (r == AFQ_OK) r = batch_step(ctx, ids, ss, branches, P, 0, 0, ctx->cs, 1);
+    if (r == AFQ_OK && launch_call_advance(ctx->cs, 2, origin) != hipSuccess)
+      r = fail(ctx, AFQ_EDEVICE, "step counter launch failed");
+    const hipError_t ec = hipStreamEndCapture(origin, &g.g);
+    if (r != AFQ_OK) {
+      if (g.g) (void)hipGraphDestroy(g.g);
+      return r;
+    }
+    if (ec != hipSuccess) return fail(ctx, AFQ_EDEVICE, std::string("capture: ") + hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&g.ex, g.g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g.g);
+      return fail(ctx, AFQ_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    if (ctx->graphs.size() >= 4) {
+      HIPCHK(hipStreamSynchronize(origin));
+      for (auto& o : ctx->graphs) {
+        (void)hipGraphExecDestroy(o.ex);
+        (void)hipGraphDestroy(o.g);
+      }
+      ctx->graphs.clear();
+    }
+    ctx->graphs.push_back(std::move(g));
+    ge = &ctx->graphs.back();
+  }
+  HIPCHK(launch_call_begin(ctx->cs, P.step0, P.n_steps, P.energies_out, origin));
+  for (int r = 0; r + 1 < P.n_steps; r += 2) HIPCHK(hipGraphLaunch(ge->ex, origin));
+  if (P.n_steps % 2) {
+    const int si = P.n_steps - 1;
+    TRY(batch_step(ctx, ids, ss, branches, P, P.step0 + (uint64_t)si, si, nullptr, 0));
   }
   return AFQ_OK;
 }
@@ -387,6 +671,23 @@ void afq_destroy(afq_ctx* ctx) {
     (void)hipEventDestroy(e.b);
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (auto& g : ctx->graphs) {
+    (void)hipGraphExecDestroy(g.ex);
+    (void)hipGraphDestroy(g.g);
+  }
+  for (auto& t : ctx->xtables) {
+    (void)hipFree(t.d_sys);
+    (void)hipFree(t.d_tiles);
+  }
+  if (ctx->cs) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->cs);
+    (void)hipEventDestroy(ctx->ev_fork);
+    for (int b = 0; b < afq_ctx::kBranches; ++b) {
+      (void)hipEventDestroy(ctx->ev_join[b]);
+      (void)hipStreamDestroy(ctx->br[b]);
+    }
+  }
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -630,9 +931,21 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     return fail(ctx, AFQ_EINVAL, "unknown precision");
   if (P->n_steps < 0) return fail(ctx, AFQ_EINVAL, "n_steps < 0");
   if (P->fields && n_sys != 1) return fail(ctx, AFQ_EINVAL, "explicit fields need a single system");
+  if (P->schedule < AFQ_SCHED_AUTO || P->schedule > AFQ_SCHED_GRAPH)
+    return fail(ctx, AFQ_EINVAL, "unknown schedule");
+  const bool batch_ok = !P->fields && P->energy_every <= 1 && !ctx->profiling;
+  int mode = P->schedule;
+  if (mode == AFQ_SCHED_AUTO)
+    mode = n_sys > 1 && batch_ok
+               ? (P->exp_method == AFQ_EXP_KRYLOV ? AFQ_SCHED_GRAPH : AFQ_SCHED_STREAMS)
+               : AFQ_SCHED_SERIAL;
+  if (mode != AFQ_SCHED_SERIAL && !batch_ok)
+    return fail(ctx, AFQ_EINVAL, "the stream and graph schedules need library fields, the energy "
+                                 "every step and profiling off");
+  if (mode == AFQ_SCHED_GRAPH && P->exp_method != AFQ_EXP_KRYLOV)
+    return fail(ctx, AFQ_EINVAL, "the graph schedule runs the Krylov exponential");
   HIPCHK(hipSetDevice(ctx->device));
   std::vector<SysDev*> ss(n_sys);
-  std::vector<double> e0(n_sys);
   for (int i = 0; i < n_sys; ++i) {
     TRY(get_sys(ctx, sys_ids[i], &ss[i]));
     if (!ss[i]->trial_ready || ss[i]->W == 0)
@@ -645,12 +958,21 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     if (P->exp_method == AFQ_EXP_KRYLOV) TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
     if (P->precision != AFQ_PREC_FP64)
       TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], P->precision == AFQ_PREC_MIXED ? 3 : 2));
-    e0[i] = std::isnan(P->e0) ? ss[i]->e_trial : P->e0;
     HIPCHK(hipMemsetAsync(ss[i]->counters, 0, 4 * sizeof(int), ctx->stream));
   }
-  for (int si = 0; si < P->n_steps; ++si)
-    for (int i = 0; i < n_sys; ++i) TRY(step_system(ctx, sys_ids[i], *ss[i], *P, si, i, e0[i]));
-  return AFQ_OK;
+  if (mode == AFQ_SCHED_SERIAL) {
+    for (int si = 0; si < P->n_steps; ++si)
+      for (int i = 0; i < n_sys; ++i) TRY(step_system(ctx, sys_ids[i], *ss[i], *P, si, i));
+    return AFQ_OK;
+  }
+  TRY(ensure_sched(ctx));
+  const auto branches = assign_branches(ss, P->exp_order);
+  if (mode == AFQ_SCHED_STREAMS) {
+    for (int si = 0; si < P->n_steps; ++si)
+      TRY(batch_step(ctx, sys_ids, ss, branches, *P, P->step0 + (uint64_t)si, si, nullptr, 0));
+    return AFQ_OK;
+  }
+  return run_graph(ctx, sys_ids, ss, branches, *P);
 } catch (...) {
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
 }

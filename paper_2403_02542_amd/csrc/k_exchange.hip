@@ -16,6 +16,9 @@
 // tile at N = 50 keeps all waves equally busy.  K is consumed in chunks of
 // 16; chunk c+1 is fetched from global memory into registers while the MFMAs
 // of chunk c run from the other half of a double-buffered LDS stage.
+#include <algorithm>
+#include <vector>
+
 #include "afq_device.h"
 #include "afq_internal.h"
 
@@ -31,28 +34,18 @@ constexpr int X_STAGE = (X_ROWS + X_COLS) * kLDK;   // LDS stage (doubles), larg
 constexpr int X_SUPER_G = 4, X_SUPER_W = 8;         // super-tile per XCD
 
 // CT: column tiles held by every wave (compile-time, >= ceil(WB 2N / 16)).
+// One tile (g-tile gt, walker tile wt) of one system.
 template <int CT>
-__global__ __launch_bounds__(XT) void k_exchange(int G1, int N, int M, int W, int GA, int WB,
-                                                 int n_gt, int n_wt, int grp,
-                                                 const double* __restrict__ Lx,
-                                                 const double* __restrict__ th_re,
-                                                 const double* __restrict__ th_im,
-                                                 double* __restrict__ ell_re,
-                                                 double* __restrict__ ell_im,
-                                                 double* __restrict__ ex_re,
-                                                 double* __restrict__ ex_im) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt, double* smem) {
+  const int G1 = p.G1, N = p.N, M = p.M, W = p.W, GA = p.GA, WB = p.WB, grp = p.grp;
+  const double* __restrict__ Lx = p.Lx;
+  const double* __restrict__ th_re = p.th_re;
+  const double* __restrict__ th_im = p.th_im;
+  double* __restrict__ ell_re = p.ell_re;
+  double* __restrict__ ell_im = p.ell_im;
+  double* __restrict__ ex_re = p.ex_re;
+  double* __restrict__ ex_im = p.ex_im;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // XCD-aware order: the blocks of one super-tile (X_SUPER_G g-tiles x
-  // X_SUPER_W walker tiles) run on one XCD and share its L2.
-  const int id = blockIdx.x;
-  const int xcd = id & 7, slot = id >> 3;
-  const int per = X_SUPER_G * X_SUPER_W;
-  const int sidx = (slot / per) * 8 + xcd, local = slot % per;
-  const int n_sw = (n_wt + X_SUPER_W - 1) / X_SUPER_W;
-  const int gt = (sidx / n_sw) * X_SUPER_G + local / X_SUPER_W;
-  const int wt = (sidx % n_sw) * X_SUPER_W + local % X_SUPER_W;
-  if (gt >= n_gt || wt >= n_wt) return;
   const int g0 = gt * GA, w0 = wt * WB;
   const int ga = min(GA, G1 - g0), wb = min(WB, W - w0);
   const int nr = ga * N, twoN = 2 * N, nc = wb * twoN;
@@ -200,6 +193,34 @@ __global__ __launch_bounds__(XT) void k_exchange(int G1, int N, int M, int W, in
   }
 }
 
+template <int CT>
+__global__ __launch_bounds__(XT) void k_exchange(XSys p, int n_gt, int n_wt) {
+  extern __shared__ double smem[];
+  // XCD-aware order: the blocks of one super-tile (X_SUPER_G g-tiles x
+  // X_SUPER_W walker tiles) run on one XCD and share its L2.
+  const int id = blockIdx.x;
+  const int xcd = id & 7, slot = id >> 3;
+  const int per = X_SUPER_G * X_SUPER_W;
+  const int sidx = (slot / per) * 8 + xcd, local = slot % per;
+  const int n_sw = (n_wt + X_SUPER_W - 1) / X_SUPER_W;
+  const int gt = (sidx / n_sw) * X_SUPER_G + local / X_SUPER_W;
+  const int wt = (sidx % n_sw) * X_SUPER_W + local % X_SUPER_W;
+  if (gt >= n_gt || wt >= n_wt) return;
+  exchange_tile_run<CT>(p, gt, wt, smem);
+}
+
+// Many systems in one launch: block b runs tile tiles[b] = (system, gt, wt).
+// The host orders the tiles by decreasing cost, so the hardware dispatcher,
+// which hands out blocks in index order as compute units free up, packs the
+// small systems' tiles around the large ones.
+template <int CT>
+__global__ __launch_bounds__(XT) void k_exchange_group(const XSys* __restrict__ sys,
+                                                       const int4* __restrict__ tiles) {
+  extern __shared__ double smem[];
+  const int4 t = tiles[blockIdx.x];
+  exchange_tile_run<CT>(sys[t.x], t.y, t.z, smem);
+}
+
 // Choose GA (g-blocks per tile) and WB (walkers per tile) for N: maximise
 // the useful fraction of the MFMA work of the busiest wave.
 void exchange_tile(int N, int& GA, int& WB) {
@@ -224,43 +245,126 @@ void exchange_tile(int N, int& GA, int& WB) {
 
 }  // namespace
 
-hipError_t launch_exchange(SysDev& s, int W, const double* th_re, const double* th_im,
-                           double* ell_re, double* ell_im, double* ex_re, double* ex_im,
-                           hipStream_t st) {
+hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const double* th_im,
+                          double* ell_re, double* ell_im, double* ex_re, double* ex_im, XSys* p,
+                          int* n_gt, int* n_wt) {
   const int N = s.N, G1 = s.G + 1;
   if (2 * N > X_COLS) return hipErrorInvalidValue;
   int GA, WB;
   exchange_tile(N, GA, WB);
-  const int n_gt = (G1 + GA - 1) / GA, n_wt = (W + WB - 1) / WB;
-  const int n_sg = (n_gt + X_SUPER_G - 1) / X_SUPER_G;
-  const int n_sw = (n_wt + X_SUPER_W - 1) / X_SUPER_W;
-  const int n_super = n_sg * n_sw;
-  const int grid = ((n_super + 7) / 8) * 8 * X_SUPER_G * X_SUPER_W;
+  if (s.x_ga > 0 && s.x_wb > 0) {   // tuned choice
+    GA = s.x_ga;
+    WB = s.x_wb;
+  }
+  if (GA * N > X_ROWS || WB * 2 * N > X_COLS || (GA * N + 15) / 16 > XW * X_RT) return hipErrorInvalidValue;
   // LDS: two stages; the epilogue reuses them for T (grp g-blocks at a time)
   // and keeps the partial sums at the end.
-  const size_t lds = sizeof(double) * 2 * X_STAGE;
   const int red_d = 4 * XW * 32;
   const int avail = 2 * X_STAGE - red_d;
   int grp = avail / (N * (2 * N + 1));
   if (grp > 32) grp = 32;
   if (grp < 1) return hipErrorInvalidValue;
   const int TC = (WB * 2 * N + 15) / 16;
-  const void* fn;
-  if (TC <= 4) fn = (const void*)k_exchange<4>;
-  else if (TC <= 7) fn = (const void*)k_exchange<7>;
-  else if (TC <= 8) fn = (const void*)k_exchange<8>;
-  else fn = (const void*)k_exchange<10>;
-  static bool lds_ok[4] = {false, false, false, false};
-  const int slot = TC <= 4 ? 0 : TC <= 7 ? 1 : TC <= 8 ? 2 : 3;
-  if (!lds_ok[slot]) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    lds_ok[slot] = true;
-  }
-  void* args[] = {(void*)&G1, (void*)&N, (void*)&s.M, (void*)&W, (void*)&GA, (void*)&WB,
-                  (void*)&n_gt, (void*)&n_wt, (void*)&grp, (void*)&s.Lx, (void*)&th_re,
-                  (void*)&th_im, (void*)&ell_re, (void*)&ell_im, (void*)&ex_re, (void*)&ex_im};
-  const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(XT), args, lds, st);
+  *p = XSys{s.Lx, th_re, th_im, ell_re, ell_im, ex_re, ex_im, G1, N, s.M, W, GA, WB, grp,
+            TC <= 4 ? 4 : TC <= 7 ? 7 : TC <= 8 ? 8 : 10};
+  *n_gt = (G1 + GA - 1) / GA;
+  *n_wt = (W + WB - 1) / WB;
+  return hipSuccess;
+}
+
+namespace {
+
+template <int CT>
+hipError_t allow_exchange_lds() {
+  static bool ok = false;
+  if (ok) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_exchange<CT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_exchange_group<CT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  ok = e == hipSuccess;
+  return e;
+}
+
+template <int CT>
+hipError_t run_exchange(const XSys& p, int n_gt, int n_wt, hipStream_t st) {
+  hipError_t e = allow_exchange_lds<CT>();
   if (e != hipSuccess) return e;
+  const int n_sg = (n_gt + X_SUPER_G - 1) / X_SUPER_G;
+  const int n_sw = (n_wt + X_SUPER_W - 1) / X_SUPER_W;
+  const int grid = ((n_sg * n_sw + 7) / 8) * 8 * X_SUPER_G * X_SUPER_W;
+  hipLaunchKernelGGL(k_exchange<CT>, dim3(grid), dim3(XT), sizeof(double) * 2 * X_STAGE, st, p,
+                     n_gt, n_wt);
   return hipGetLastError();
+}
+
+template <int CT>
+hipError_t run_exchange_group(const XSys* d_sys, const int4* d_tiles, int n_tiles, hipStream_t st) {
+  hipError_t e = allow_exchange_lds<CT>();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_exchange_group<CT>, dim3(n_tiles), dim3(XT), sizeof(double) * 2 * X_STAGE,
+                     st, d_sys, d_tiles);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_exchange(SysDev& s, int W, const double* th_re, const double* th_im,
+                           double* ell_re, double* ell_im, double* ex_re, double* ex_im,
+                           hipStream_t st) {
+  XSys p;
+  int n_gt, n_wt;
+  hipError_t e = exchange_setup(s, W, th_re, th_im, ell_re, ell_im, ex_re, ex_im, &p, &n_gt, &n_wt);
+  if (e != hipSuccess) return e;
+  switch (p.ct) {
+    case 4: return run_exchange<4>(p, n_gt, n_wt, st);
+    case 7: return run_exchange<7>(p, n_gt, n_wt, st);
+    case 8: return run_exchange<8>(p, n_gt, n_wt, st);
+    default: return run_exchange<10>(p, n_gt, n_wt, st);
+  }
+}
+
+void exchange_tile_order(int n_gt, int n_wt, std::vector<int2>& out) {
+  // the single-system kernel's XCD super-tile order, invalid slots dropped
+  const int n_sg = (n_gt + X_SUPER_G - 1) / X_SUPER_G;
+  const int n_sw = (n_wt + X_SUPER_W - 1) / X_SUPER_W;
+  const int per = X_SUPER_G * X_SUPER_W;
+  const int grid = ((n_sg * n_sw + 7) / 8) * 8 * per;
+  for (int id = 0; id < grid; ++id) {
+    const int xcd = id & 7, slot = id >> 3;
+    const int sidx = (slot / per) * 8 + xcd, local = slot % per;
+    const int gt = (sidx / n_sw) * X_SUPER_G + local / X_SUPER_W;
+    const int wt = (sidx % n_sw) * X_SUPER_W + local % X_SUPER_W;
+    if (gt < n_gt && wt < n_wt) out.push_back(int2{gt, wt});
+  }
+}
+
+hipError_t launch_exchange_group(int ct, const XSys* d_sys, const int4* d_tiles, int n_tiles,
+                                 hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (ct) {
+    case 4: return run_exchange_group<4>(d_sys, d_tiles, n_tiles, st);
+    case 7: return run_exchange_group<7>(d_sys, d_tiles, n_tiles, st);
+    case 8: return run_exchange_group<8>(d_sys, d_tiles, n_tiles, st);
+    case 10: return run_exchange_group<10>(d_sys, d_tiles, n_tiles, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Tile shapes the model admits for N, best first (candidates of the tuner).
+void exchange_candidates(int N, std::vector<int2>& out) {
+  struct C { double eff; int ga, wb; };
+  std::vector<C> cs;
+  for (int ga = 1; ga * N <= X_ROWS; ++ga)
+    for (int wb = 1; wb * 2 * N <= X_COLS; ++wb) {
+      const int TR = (ga * N + 15) / 16, TC = (wb * 2 * N + 15) / 16;
+      const int rpw = (TR + XW - 1) / XW;
+      if (rpw > X_RT || TC > X_CTMAX) continue;
+      const double useful = (double)ga * N * wb * 2 * N;
+      const double work = (double)XW * rpw * TC * 256.0;
+      cs.push_back(C{useful / work + 1e-6 * ga * wb, ga, wb});
+    }
+  std::sort(cs.begin(), cs.end(), [](const C& a, const C& b) { return a.eff > b.eff; });
+  for (const C& c : cs) out.push_back(int2{c.ga, c.wb});
 }

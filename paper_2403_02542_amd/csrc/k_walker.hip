@@ -43,10 +43,11 @@ AFQ_DEV U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
 // x[w][g], block b of walker w covers g = 4b .. 4b+3.  Philox counter of the
 // block: (step * W + w) * ceil(G/4) + b + 1 (the first counter value is 1).
 __global__ void k_fields(uint64_t seed, uint64_t sid, uint64_t step, int W, int G,
-                         double* __restrict__ out) {
+                         double* __restrict__ out, const CallState* __restrict__ cs, int add) {
   const int nb = (G + 3) / 4;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)W * nb) return;
+  if (cs) step = cs->step + (uint64_t)add;
   const int w = (int)(t / nb), b = (int)(t % nb);
   U64x4 c;
   c.v[0] = ((uint64_t)step * W + w) * nb + b + 1;
@@ -406,13 +407,24 @@ __global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ p
                                             double* __restrict__ ph_im,
                                             double* __restrict__ qr_logr,
                                             int* __restrict__ bad,
-                                            const int* __restrict__ alive) {
+                                            const int* __restrict__ alive,
+                                            const CallState* __restrict__ cs, int add,
+                                            int every) {
   extern __shared__ double smem[];
   double* stage = smem;
   double* S = stage + SM_STAGE;           // N x N complex: S, then R, then R^-1
   double* col = S + 2 * N * N;            // 2N
   double* fail = col + 2 * N;             // failure flag of the factorisation
   const int w = blockIdx.x;
+  if (cs) {
+    // schedule read from the device step counter: QR after step t when
+    // (t + 1) % every == 0; otherwise the step's log det R is 0
+    const uint64_t t = cs->step + (uint64_t)add;
+    if (!(every > 0 && (t + 1) % (uint64_t)every == 0)) {
+      if (threadIdx.x == 0) qr_logr[w] = 0.0;
+      return;
+    }
+  }
   if (!alive[w] || bad[w]) return;
   const int64_t off = (int64_t)w * N * M;
   double* pr = ph_re + off;
@@ -573,8 +585,12 @@ __global__ __launch_bounds__(256) void k_energy(int G, int G1, double e_core,
 __global__ __launch_bounds__(256) void k_estimator(int W, const double* __restrict__ weight,
                                                    const double* __restrict__ ecap,
                                                    const int* __restrict__ alive,
-                                                   double* __restrict__ out2, int* __restrict__ nlive) {
+                                                   double* __restrict__ out2, int* __restrict__ nlive,
+                                                   const CallState* __restrict__ cs, int add,
+                                                   int64_t row) {
   __shared__ double red[4];
+  if (cs && cs->energies)
+    out2 = cs->energies + (row * cs->n_steps + (int64_t)(cs->step + (uint64_t)add - cs->step0)) * 2;
   double a = 0.0, b = 0.0, c = 0.0;
   for (int w = threadIdx.x; w < W; w += 256) {
     if (alive[w]) {
@@ -652,9 +668,34 @@ bool g_lds_overlap = false, g_lds_qr = false;
 // ==================================================================== launchers
 
 hipError_t launch_fields(uint64_t seed, uint64_t sid, uint64_t step, int W, int G, double* out,
-                         hipStream_t st) {
+                         hipStream_t st, const CallState* cs, int add) {
   const int64_t n = (int64_t)W * ((G + 3) / 4);
-  hipLaunchKernelGGL(k_fields, dim3(nblk(n, 256)), dim3(256), 0, st, seed, sid, step, W, G, out);
+  hipLaunchKernelGGL(k_fields, dim3(nblk(n, 256)), dim3(256), 0, st, seed, sid, step, W, G, out,
+                     cs, add);
+  return hipGetLastError();
+}
+
+__global__ void k_call_begin(CallState* cs, uint64_t step0, int64_t n_steps, double* energies) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    cs->step = step0;
+    cs->step0 = step0;
+    cs->n_steps = n_steps;
+    cs->energies = energies;
+  }
+}
+
+__global__ void k_call_advance(CallState* cs, int n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) cs->step += (uint64_t)n;
+}
+
+hipError_t launch_call_begin(CallState* cs, uint64_t step0, int64_t n_steps, double* energies,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_call_begin, dim3(1), dim3(64), 0, st, cs, step0, n_steps, energies);
+  return hipGetLastError();
+}
+
+hipError_t launch_call_advance(CallState* cs, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_call_advance, dim3(1), dim3(64), 0, st, cs, n);
   return hipGetLastError();
 }
 
@@ -699,14 +740,15 @@ hipError_t launch_weight(SysDev& s, double tau, double e0, const double* qr_logr
   return hipGetLastError();
 }
 
-hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st) {
+hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st,
+                     const CallState* cs, int add, int every) {
   if (2 * s.N > SM_ROWS) return hipErrorInvalidValue;
   const size_t lds = qr_lds(s.N);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = allow_full_lds((const void*)k_qr, g_lds_qr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qr, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, qr_logr, s.bad,
-                     s.alive);
+                     s.alive, cs, add, every);
   return hipGetLastError();
 }
 
@@ -729,9 +771,10 @@ hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* e
   return hipGetLastError();
 }
 
-hipError_t launch_estimator(SysDev& s, double* out2, hipStream_t st) {
+hipError_t launch_estimator(SysDev& s, double* out2, hipStream_t st, const CallState* cs, int add,
+                            int64_t row) {
   hipLaunchKernelGGL(k_estimator, dim3(1), dim3(256), 0, st, s.W, s.weight, s.ecap, s.alive, out2,
-                     s.counters ? s.counters + 0 : nullptr);
+                     s.counters ? s.counters + 0 : nullptr, cs, add, row);
   return hipGetLastError();
 }
 

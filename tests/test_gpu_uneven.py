@@ -1,0 +1,127 @@
+"""Many systems of uneven size in one propagate call: every schedule (one
+system after another, branch streams with the many-system local-energy
+launch, captured two-step graph) gives bitwise the same walkers and
+energies as each system propagated alone, and the tracked walkers follow
+the oracle.  Plus the largest shape of the uneven batch (N = 65) against the
+oracle step by step."""
+import numpy as np
+import pytest
+
+import afq_workloads as W
+import gpu_common as C
+from oracle import afq_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+# five systems, M from 16 to 140, 8 walkers, QR every 2 steps, an odd number
+# of steps (the graph schedule replays two-step graphs and ends with one
+# stream step)
+SMALL = W.UnevenBatch("u5", n_sys=5, W=8, tau=0.05, k=6, steps=7, reorth_every=2, m_lo=16,
+                      m_hi=140, seed=3)
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    C.require_gpu()
+    return W.make_uneven_batch(SMALL)
+
+
+def _run(batch, schedule, alone=False):
+    import torch
+    from paper_2403_02542_amd import afq
+    ctx = afq.Context(0)
+    ids = []
+    for cfg, ham, psi in batch:
+        sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+        ctx.init_trial(sid, psi)
+        ctx.init_walkers(sid, SMALL.W)
+        ids.append(sid)
+    n = len(ids)
+    en = torch.zeros((n, SMALL.steps, 2), dtype=torch.float64, device="cuda")
+    kw = dict(tau=SMALL.tau, n_steps=SMALL.steps, exp_method=afq.EXP_KRYLOV, exp_order=SMALL.k,
+              reorth_every=SMALL.reorth_every, seed=0, schedule=schedule)
+    if alone:
+        for i, sid in enumerate(ids):
+            ctx.propagate_batch(sid, energies_out=en[i:i + 1], **kw)
+    else:
+        ctx.propagate_batch(ids, energies_out=en, **kw)
+    ctx.sync()
+    torch.cuda.synchronize()
+    out = [ctx.get_walkers(sid) for sid in ids]
+    el = [ctx.local_energy_batch(sid) for sid in ids]
+    e = en.cpu().numpy()
+    ctx.close()
+    return out, el, e
+
+
+def test_uneven_schedules_bitwise_and_oracle(small_batch):
+    from paper_2403_02542_amd import afq
+    ref, ref_el, ref_e = _run(small_batch, afq.SCHED_SERIAL, alone=True)
+    for sched in (afq.SCHED_SERIAL, afq.SCHED_STREAMS, afq.SCHED_GRAPH):
+        out, el, e = _run(small_batch, sched)
+        print(f"  schedule {sched}: compared", flush=True)
+        assert np.array_equal(e, ref_e), sched
+        for i in range(len(out)):
+            for key in ("phi", "weight", "log_ovlp", "alive"):
+                assert np.array_equal(out[i][key], ref[i][key]), (sched, i, key)
+            assert np.array_equal(el[i], ref_el[i]), (sched, i)
+    # one tracked walker per system against the oracle
+    for i, (cfg, ham, psi) in enumerate(small_batch):
+        p = O.prepare(ham.h, ham.L, ham.e_core, psi, SMALL.tau)
+        w = i % SMALL.W
+        wk = O.init_walker(p)
+        flagged = False
+        for t in range(SMALL.steps):
+            x = W.fields(0, i, t, SMALL.W, cfg.G)[w]
+            wk, info = O.walker_step(p, wk, x, O.EXP_KRYLOV, SMALL.k,
+                                     O.reorth_due(t, SMALL.reorth_every))
+            flagged = flagged or C.flags_from_info(p, info)
+        print(f"  system {i} (M={cfg.M}, N={cfg.N}, G={cfg.G}) walker {w}: flagged {flagged}",
+              flush=True)
+        if flagged:
+            continue
+        assert C.rel(ref[i]["phi"][w], wk.phi) < C.RTOL
+        assert abs(ref[i]["weight"][w] - wk.weight) < C.RTOL * max(1.0, abs(wk.weight))
+        assert abs(ref_el[i][w] - info.e_loc) < C.RTOL * max(1.0, abs(info.e_loc))
+
+
+def test_schedule_argument_errors(small_batch):
+    import torch
+    from paper_2403_02542_amd import afq
+    ctx = afq.Context(0)
+    ids = []
+    for cfg, ham, psi in small_batch[:2]:
+        sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+        ctx.init_trial(sid, psi)
+        ctx.init_walkers(sid, 4)
+        ids.append(sid)
+    with pytest.raises(afq.AfqError):
+        ctx.propagate_batch(ids, tau=0.05, n_steps=1, exp_method=afq.EXP_TAYLOR,
+                            schedule=afq.SCHED_GRAPH)
+    x = torch.zeros((1, 4, small_batch[0][0].G), dtype=torch.float64, device="cuda")
+    with pytest.raises(afq.AfqError):
+        ctx.propagate_batch(ids[:1], tau=0.05, n_steps=1, fields=x, schedule=afq.SCHED_STREAMS)
+    with pytest.raises(afq.AfqError):
+        ctx.propagate_batch(ids, tau=0.05, n_steps=2, energy_every=2, schedule=afq.SCHED_GRAPH)
+    with pytest.raises(afq.AfqError):
+        ctx.propagate_batch(ids, tau=0.05, n_steps=1, schedule=7)
+    ctx.close()
+
+
+def test_largest_uneven_shape_single_step():
+    """M = 390, N = 65, G = 1950 (the largest system of the 48-system batch),
+    64 walkers; the oracle restarted from the GPU state every step."""
+    C.require_gpu()
+    from paper_2403_02542_amd import afq
+    sizes = [c.M for c in W.C4.configs()]
+    big = int(np.argmax(sizes))
+    (cfg, ham, psi), = W.make_uneven_batch(W.C4, only=[big])
+    case = C.Case(ham.h, ham.L, psi, ham.e_core)
+    ctx = afq.Context(0)
+    worst, flagged, sid = C.run_pair(case, ctx, tau=cfg.tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                     reorth=cfg.reorth_every, n_steps=3, n_walkers=cfg.W,
+                                     track=[0, 63], resync=True)
+    ctx.close()
+    print("largest uneven shape", cfg, worst, "flagged", sorted(flagged))
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
