@@ -134,6 +134,18 @@ enum { AFQ_SCHED_AUTO = 0, AFQ_SCHED_SERIAL = 1, AFQ_SCHED_STREAMS = 2, AFQ_SCHE
 afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys,
                                const afq_prop_params* params);
 
+/* Tile shapes from measurement.  For each listed system (with walkers), the
+ * local-energy contraction is timed with the six tile shapes (Cholesky
+ * blocks x walkers per workgroup) its occupancy model ranks best, and the
+ * operator-orbital product with 1x, 2x, 4x ... its default number of column
+ * blocks; each launch is timed `reps` times (< 1: 3) after a warm-up launch
+ * on the context stream, with the system's current walkers and outputs to
+ * scratch memory.  The fastest shapes are kept by the system and used by
+ * every later call.  Walker state is not changed, and later results do not
+ * depend on the choice (every output is the same sum in the same order).
+ * Synchronises the context stream. */
+afq_status afq_autotune(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys, int32_t reps);
+
 /* Local energy of every walker (Eq. eloc) at its current determinant:
  * eloc_out complex128 [W].  The Coulomb vector ell_g = <Lhat_g>_mixed,
  * complex128 [W][n_chol], is written to ell_out if it is not NULL.

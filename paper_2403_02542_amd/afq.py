@@ -27,7 +27,7 @@ EXPORTED = (
     "afq_init_walkers", "afq_propagate_batch", "afq_local_energy_batch",
     "afq_local_energy_adjoint", "afq_force_bias_adjoint", "afq_get_walkers",
     "afq_set_walkers", "afq_fill_fields", "afq_get_counters", "afq_profile",
-    "afq_profile_read", "afq_sync",
+    "afq_profile_read", "afq_sync", "afq_autotune",
 )
 PHASES = ("fields", "force_bias", "opbuild", "onebody", "exponential", "overlap", "weight", "qr",
           "exchange", "energy")
@@ -82,6 +82,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "afq_profile": (i32, [P, ctypes.c_int]),
         "afq_profile_read": (i32, [P, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]),
         "afq_sync": (i32, [P]),
+        "afq_autotune": (i32, [P, ctypes.POINTER(i32), i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -194,6 +195,12 @@ class Context:
                          math.nan if e0 is None else float(e0), int(seed), int(step0), fp, ep,
                          int(schedule))
         self._check(self._lib.afq_propagate_batch(self._h, arr, len(ids), ctypes.byref(prm)))
+
+    def autotune(self, sys_ids, reps: int = 3, **_ignored):
+        """Measure and keep the fastest tile shapes of the listed systems."""
+        ids = [sys_ids] if isinstance(sys_ids, int) else list(sys_ids)
+        arr = (ctypes.c_int32 * len(ids))(*ids)
+        self._check(self._lib.afq_autotune(self._h, arr, len(ids), int(reps)))
 
     def local_energy_batch(self, sys_id: int, eloc_out=None, ell_out=None, precision=PREC_FP64):
         W, G = self.dims[sys_id]["W"], self.dims[sys_id]["G"]

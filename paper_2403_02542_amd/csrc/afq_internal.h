@@ -164,6 +164,13 @@ void exchange_tile_order(int n_gt, int n_wt, std::vector<int2>& out);
 // instance ct; d_sys and d_tiles are device tables.
 hipError_t launch_exchange_group(int ct, const XSys* d_sys, const int4* d_tiles, int n_tiles,
                                  hipStream_t st);
+// Column blocks of the operator-orbital product: default and largest
+// admissible count (each block holds at most 8 column tiles of 16).
+int matvec_default_blocks(int M);
+int matvec_max_blocks(int M);
+// One operator-orbital product out = A in over all walkers (tuner probe).
+hipError_t launch_matvec_probe(SysDev& s, const double* in_re, const double* in_im, double* out_re,
+                               double* out_im, hipStream_t st);
 // Admissible (GA, WB) tile shapes for N, best first by the occupancy model.
 void exchange_candidates(int N, std::vector<int2>& out);
 hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* ell_im,

@@ -552,6 +552,9 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
     put_bytes(key, ss[i]->th_re);
     put_bytes(key, ss[i]->phi_re);
     put_bytes(key, e0_of(*ss[i], P));
+    put_bytes(key, ss[i]->x_ga);
+    put_bytes(key, ss[i]->x_wb);
+    put_bytes(key, ss[i]->mv_ct);
   }
   put_bytes(key, P.tau);
   put_bytes(key, P.exp_method);
@@ -973,6 +976,94 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     return AFQ_OK;
   }
   return run_graph(ctx, sys_ids, ss, branches, *P);
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_autotune(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys, int32_t reps) try {
+  if (!ctx) return AFQ_EINVAL;
+  if (!sys_ids || n_sys < 1) return fail(ctx, AFQ_EINVAL, "bad arguments");
+  if (reps < 1) reps = 3;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIPCHK(hipEventCreate(&ea));
+  HIPCHK(hipEventCreate(&eb));
+  std::vector<void*> tmp;
+  afq_status r = AFQ_OK;
+  // time `reps` launches after one warm-up launch
+  auto time_it = [&](auto&& launch, float* ms) -> afq_status {
+    HIPCHK(launch());
+    HIPCHK(hipEventRecord(ea, ctx->stream));
+    for (int i = 0; i < reps; ++i) HIPCHK(launch());
+    HIPCHK(hipEventRecord(eb, ctx->stream));
+    HIPCHK(hipEventSynchronize(eb));
+    HIPCHK(hipEventElapsedTime(ms, ea, eb));
+    return AFQ_OK;
+  };
+  for (int i = 0; i < n_sys && r == AFQ_OK; ++i) {
+    SysDev* sp;
+    r = get_sys(ctx, sys_ids[i], &sp);
+    if (r != AFQ_OK) break;
+    SysDev& s = *sp;
+    if (!s.W) {
+      r = fail(ctx, AFQ_ESTATE, "system " + std::to_string(sys_ids[i]) + " has no walkers");
+      break;
+    }
+    // local-energy contraction: the model's six best tile shapes, outputs to scratch
+    const size_t n = (size_t)s.W * (s.G + 1);
+    double *lr, *li, *xr, *xi;
+    if ((r = dalloc(ctx, tmp, &lr, n)) != AFQ_OK) break;
+    if ((r = dalloc(ctx, tmp, &li, n)) != AFQ_OK) break;
+    if ((r = dalloc(ctx, tmp, &xr, n)) != AFQ_OK) break;
+    if ((r = dalloc(ctx, tmp, &xi, n)) != AFQ_OK) break;
+    std::vector<int2> cand;
+    exchange_candidates(s.N, cand);
+    if (cand.size() > 6) cand.resize(6);
+    float best = 1e30f;
+    int bga = 0, bwb = 0;
+    for (const int2& c : cand) {
+      s.x_ga = c.x;
+      s.x_wb = c.y;
+      float ms = 0.f;
+      r = time_it([&] { return launch_exchange(s, s.W, s.th_re, s.th_im, lr, li, xr, xi, ctx->stream); },
+                  &ms);
+      if (r != AFQ_OK) break;
+      if (ms < best) {
+        best = ms;
+        bga = c.x;
+        bwb = c.y;
+      }
+    }
+    s.x_ga = bga;
+    s.x_wb = bwb;
+    if (r != AFQ_OK) break;
+    // operator-orbital product (Krylov or Taylor): column-block counts
+    if (s.A_re) {
+      const int base = matvec_default_blocks(s.M), top = matvec_max_blocks(s.M);
+      std::vector<int> nct;
+      for (int c = base; c < top; c *= 2) nct.push_back(c);
+      nct.push_back(top);
+      best = 1e30f;
+      int bct = 0;
+      for (int c : nct) {
+        s.mv_ct = c;
+        float ms = 0.f;
+        r = time_it([&] { return launch_matvec_probe(s, s.phi_re, s.phi_im, s.t3_re, s.t3_im,
+                                                     ctx->stream); }, &ms);
+        if (r != AFQ_OK) break;
+        if (ms < best) {
+          best = ms;
+          bct = c;
+        }
+      }
+      s.mv_ct = bct;
+    }
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  free_all(tmp);
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  return r;
 } catch (...) {
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
 }

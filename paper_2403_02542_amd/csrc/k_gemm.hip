@@ -305,7 +305,7 @@ hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecO
     if (e != hipSuccess) return e;
     lds_ok = true;
   }
-  const int n_ct = matvec_col_blocks(s.M);
+  const int n_ct = s.mv_ct > 0 ? s.mv_ct : matvec_col_blocks(s.M);
   hipLaunchKernelGGL(k_matvec<RT>, dim3(xcd_grid(s.W, n_ct)), dim3(P::NT), P::LDS_BYTES, st, s.W,
                      s.N, s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
   return hipGetLastError();
@@ -532,6 +532,18 @@ __global__ __launch_bounds__(256) void k_krylov_combine(int WN, int M, int kmax,
 }
 
 }  // namespace
+
+int matvec_default_blocks(int M) { return matvec_col_blocks(M); }
+
+int matvec_max_blocks(int M) { return (M + 15) / 16; }
+
+hipError_t launch_matvec_probe(SysDev& s, const double* in_re, const double* in_im, double* out_re,
+                               double* out_im, hipStream_t st) {
+  const int64_t sw = (int64_t)s.N * s.M;
+  VecRef v{in_re, in_im, sw, s.M};
+  VecOut o{out_re, out_im, sw, s.M};
+  return run_matvec(s, v, o, 0, 1.0, o, st);
+}
 
 // ==================================================================== launchers
 

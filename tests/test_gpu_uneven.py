@@ -26,7 +26,7 @@ def small_batch():
     return W.make_uneven_batch(SMALL)
 
 
-def _run(batch, schedule, alone=False):
+def _run(batch, schedule, alone=False, tune=False):
     import torch
     from paper_2403_02542_amd import afq
     ctx = afq.Context(0)
@@ -37,6 +37,8 @@ def _run(batch, schedule, alone=False):
         ctx.init_walkers(sid, SMALL.W)
         ids.append(sid)
     n = len(ids)
+    if tune:
+        ctx.autotune(ids)
     en = torch.zeros((n, SMALL.steps, 2), dtype=torch.float64, device="cuda")
     kw = dict(tau=SMALL.tau, n_steps=SMALL.steps, exp_method=afq.EXP_KRYLOV, exp_order=SMALL.k,
               reorth_every=SMALL.reorth_every, seed=0, schedule=schedule)
@@ -83,6 +85,19 @@ def test_uneven_schedules_bitwise_and_oracle(small_batch):
         assert C.rel(ref[i]["phi"][w], wk.phi) < C.RTOL
         assert abs(ref[i]["weight"][w] - wk.weight) < C.RTOL * max(1.0, abs(wk.weight))
         assert abs(ref_el[i][w] - info.e_loc) < C.RTOL * max(1.0, abs(info.e_loc))
+
+
+def test_autotuned_tiles_keep_results(small_batch):
+    """Tuned tile shapes change which workgroup computes what, not the sums:
+    results stay bitwise equal to the untuned run."""
+    from paper_2403_02542_amd import afq
+    ref, ref_el, ref_e = _run(small_batch, afq.SCHED_SERIAL)
+    out, el, e = _run(small_batch, afq.SCHED_GRAPH, tune=True)
+    assert np.array_equal(e, ref_e)
+    for i in range(len(out)):
+        for key in ("phi", "weight", "log_ovlp", "alive"):
+            assert np.array_equal(out[i][key], ref[i][key]), (i, key)
+        assert np.array_equal(el[i], ref_el[i]), i
 
 
 def test_schedule_argument_errors(small_batch):
