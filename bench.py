@@ -391,7 +391,8 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--tau", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_fast"])
+    ap.add_argument("--precision", default="fp64",
+                    choices=["fp64", "mixed", "mixed_fast", "mixed_energy"])
     ap.add_argument("--cpu-procs", type=int, default=None,
                     help="oracle processes for the CPU baseline (default: host cores, <= 16)")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -449,8 +450,8 @@ def main():
     sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
     ctx.init_trial(sid, psi)
     ctx.init_walkers(sid, cfg.W)
-    prec = {"fp64": afq.PREC_FP64, "mixed": afq.PREC_MIXED,
-            "mixed_fast": afq.PREC_MIXED_FAST}[args.precision]
+    prec = {"fp64": afq.PREC_FP64, "mixed": afq.PREC_MIXED, "mixed_fast": afq.PREC_MIXED_FAST,
+            "mixed_energy": afq.PREC_MIXED_ENERGY}[args.precision]
     kw = dict(tau=cfg.tau, exp_method=afq.EXP_KRYLOV, exp_order=cfg.k,
               reorth_every=cfg.reorth_every, seed=0, precision=prec)
     energies = torch.zeros((1, args.steps, 2), dtype=torch.float64, device="cuda")

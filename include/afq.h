@@ -49,8 +49,15 @@ enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1 };
 /* Precision of the dense contractions: FP64, or BF16-split operands on the
  * BF16 matrix cores with FP32 accumulation, three pieces per value (six
  * piece products, ~24 significand bits) or two pieces (three products, ~16
- * bits).  Overlap, inverse, QR, weights and energy sums stay FP64. */
-enum { AFQ_PREC_FP64 = 0, AFQ_PREC_MIXED = 1, AFQ_PREC_MIXED_FAST = 2 };
+ * bits).
+ *  MIXED:        local energy / Coulomb vector, operator build, one-body
+ *                half-steps (as Phi + (B - I) Phi) and the operator-orbital
+ *                products of the exponential, three pieces.
+ *  MIXED_FAST:   the same with two pieces.
+ *  MIXED_ENERGY: only the local-energy / Coulomb-vector contraction, three
+ *                pieces; propagation in FP64.
+ * Overlap, inverse, QR, Arnoldi, weights and energy sums stay FP64. */
+enum { AFQ_PREC_FP64 = 0, AFQ_PREC_MIXED = 1, AFQ_PREC_MIXED_FAST = 2, AFQ_PREC_MIXED_ENERGY = 3 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
  * enqueue on, or NULL for a stream owned by the context (default priority). */

@@ -356,3 +356,226 @@ AFQ_DEV float bf16_bits_to_f(unsigned short b) { return __uint_as_float((unsigne
 AFQ_DEV f4_t mfma_bf16(const bf8_t& a, const bf8_t& b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+
+// ---------------------------------------------------------------- BF16-split pipelined engine
+// The FP64 engine's contract (C[r][c] = sum_k A(r, k) B(c, k), float64
+// getters) on the BF16 matrix cores: operands are read as float64, split into
+// P bfloat16 pieces while they are staged in LDS ([piece][row][k], pitch 40),
+// and the piece products (3 for P = 2, 6 for P = 3) accumulate in FP32.  K
+// runs in chunks of 32 (one MFMA k-step) through two LDS stages with the next
+// chunk prefetched into registers.  Each thread stages units of four
+// consecutive k of one row (one 8-byte LDS store per piece).
+template <int P>
+struct SplitProds;
+template <>
+struct SplitProds<2> {
+  static constexpr int N = 3;
+  static constexpr int a[3] = {0, 0, 1};
+  static constexpr int b[3] = {0, 1, 0};
+};
+template <>
+struct SplitProds<3> {
+  static constexpr int N = 6;
+  static constexpr int a[6] = {0, 0, 1, 1, 0, 2};
+  static constexpr int b[6] = {0, 1, 0, 1, 2, 0};
+};
+
+template <int WR, int WC, int RT, int CT, int P>
+struct PipeMx {
+  static constexpr int NW = WR * WC;
+  static constexpr int NT = NW * 64;
+  static constexpr int ROWS = WR * RT * 16;
+  static constexpr int COLS = WC * CT * 16;
+  static constexpr int KC = 32;
+  static constexpr int PITCH = 40;                        // bf16 per staged row
+  static constexpr int STAGE = P * (ROWS + COLS) * PITCH; // bf16 per stage
+  static constexpr int UNITS = (ROWS + COLS) * (KC / 4);  // 4-k units per chunk
+  static constexpr int PF = (UNITS + NT - 1) / NT;
+  static constexpr size_t LDS_BYTES = 2 * (size_t)STAGE * 2;
+};
+
+template <int WR, int WC, int RT, int CT, int P, bool A_KM, bool B_KM, class GA, class GB>
+AFQ_DEV PipeSplit pipe_gemm_mx(int K, int nr, int nc, GA ga, GB gb, unsigned short* smem,
+                               f4_t (&acc)[RT][CT]) {
+  using Q = PipeMx<WR, WC, RT, CT, P>;
+  constexpr int KU = Q::KC / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int TR = (nr + 15) >> 4, TC = (nc + 15) >> 4;
+  const int rpw = (TR + WR - 1) / WR, cpw = (TC + WC - 1) / WC;
+  PipeSplit sp;
+  sp.rt0 = wr * rpw;
+  sp.mtv = max(0, min(min(rpw, RT), TR - sp.rt0));
+  sp.ct0 = wc * cpw;
+  sp.ntv = max(0, min(min(cpw, CT), TC - sp.ct0));
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+  double pf[Q::PF][4];
+  // unit u -> (stage row, first k of the unit)
+  auto slot = [&](int u, int& row, int& k) {
+    if (u < Q::ROWS * KU) {
+      if (A_KM) {
+        k = (u / Q::ROWS) * 4;
+        row = u % Q::ROWS;
+      } else {
+        row = u / KU;
+        k = (u % KU) * 4;
+      }
+    } else {
+      const int u2 = u - Q::ROWS * KU;
+      int c;
+      if (B_KM) {
+        k = (u2 / Q::COLS) * 4;
+        c = u2 % Q::COLS;
+      } else {
+        c = u2 / KU;
+        k = (u2 % KU) * 4;
+      }
+      row = Q::ROWS + c;
+    }
+  };
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < Q::PF; ++i) {
+      const int u = tid + i * Q::NT;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) pf[i][t] = 0.0;
+      if (u < Q::UNITS) {
+        int row, k;
+        slot(u, row, k);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int kg = k0 + k + t;
+          if (kg < K) {
+            if (row < Q::ROWS) {
+              if (row < nr) pf[i][t] = ga(row, kg);
+            } else if (row - Q::ROWS < nc) {
+              pf[i][t] = gb(row - Q::ROWS, kg);
+            }
+          }
+        }
+      }
+    }
+  };
+  auto store = [&](unsigned short* S) {
+#pragma unroll
+    for (int i = 0; i < Q::PF; ++i) {
+      const int u = tid + i * Q::NT;
+      if (u < Q::UNITS) {
+        int row, k;
+        slot(u, row, k);
+        double x[4] = {pf[i][0], pf[i][1], pf[i][2], pf[i][3]};
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          unsigned short b[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            b[t] = bf16_bits_rn((float)x[t]);
+            x[t] -= (double)bf16_bits_to_f(b[t]);
+          }
+          uint2 v;
+          v.x = (unsigned)b[0] | ((unsigned)b[1] << 16);
+          v.y = (unsigned)b[2] | ((unsigned)b[3] << 16);
+          *(uint2*)(S + ((size_t)p * (Q::ROWS + Q::COLS) + row) * Q::PITCH + k) = v;
+        }
+      }
+    }
+  };
+  const int nchunk = (K + Q::KC - 1) / Q::KC;
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  fetch(0);
+  store(smem);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const unsigned short* S = smem + (size_t)(ch & 1) * Q::STAGE;
+    if (ch + 1 < nchunk) fetch((ch + 1) * Q::KC);
+    bf8_t a[RT][P], b[CT][P];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (i < sp.mtv)
+          a[i][p] = *(const bf8_t*)(S + ((size_t)p * (Q::ROWS + Q::COLS) + (sp.rt0 + i) * 16 + lr) *
+                                            Q::PITCH + lk);
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (j < sp.ntv)
+          b[j][p] = *(const bf8_t*)(S + ((size_t)p * (Q::ROWS + Q::COLS) + Q::ROWS +
+                                         (sp.ct0 + j) * 16 + lr) * Q::PITCH + lk);
+#pragma unroll
+    for (int q = 0; q < SplitProds<P>::N; ++q)
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        if (i >= sp.mtv) continue;
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+          if (j < sp.ntv)
+            acc[i][j] = mfma_bf16(a[i][SplitProds<P>::a[q]], b[j][SplitProds<P>::b[q]], acc[i][j]);
+      }
+    if (ch + 1 < nchunk) store(smem + (size_t)((ch + 1) & 1) * Q::STAGE);
+    __syncthreads();
+  }
+  return sp;
+}
+
+// Row / column (within the tile) of FP32 accumulator element e of tile (i, j).
+AFQ_DEV int pipe_mx_row(const PipeSplit& sp, int i, int e) {
+  return (sp.rt0 + i) * 16 + 4 * ((threadIdx.x & 63) >> 4) + e;
+}
+AFQ_DEV int pipe_mx_col(const PipeSplit& sp, int j) { return (sp.ct0 + j) * 16 + (threadIdx.x & 15); }
+
+// Visit every valid accumulator element of an engine tile: f(row, col, value)
+// in tile coordinates (rows / columns beyond the tile's extent are skipped
+// by the caller's bounds in f).
+template <int RT, int CT, class F>
+AFQ_DEV void pipe_emit(const PipeSplit& sp, d4_t (&acc)[RT][CT], F f) {
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      if (i >= sp.mtv || j >= sp.ntv) continue;
+      const int c = pipe_col(sp, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f(pipe_row(sp, i, e), c, acc[i][j][e]);
+    }
+}
+template <int RT, int CT, class F>
+AFQ_DEV void pipe_emit(const PipeSplit& sp, f4_t (&acc)[RT][CT], F f) {
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      if (i >= sp.mtv || j >= sp.ntv) continue;
+      const int c = pipe_mx_col(sp, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f(pipe_mx_row(sp, i, e), c, (double)acc[i][j][e]);
+    }
+}
+
+// C tile of the FP64 engine (PC = 0) or of the BF16-split engine with PC
+// pieces, then f(row, col, value) for every element.
+template <int WR, int WC, int RT, int CT, int PC, bool A_KM, bool B_KM, int BK = 16, class GA,
+          class GB, class F>
+AFQ_DEV void pipe_run(int K, int nr, int nc, GA ga, GB gb, double* smem, F f) {
+  if constexpr (PC == 0) {
+    d4_t acc[RT][CT];
+    const PipeSplit sp = pipe_gemm<WR, WC, RT, CT, A_KM, B_KM, BK>(K, nr, nc, ga, gb, smem, acc);
+    pipe_emit(sp, acc, f);
+  } else {
+    f4_t acc[RT][CT];
+    const PipeSplit sp = pipe_gemm_mx<WR, WC, RT, CT, PC, A_KM, B_KM>(
+        K, nr, nc, ga, gb, reinterpret_cast<unsigned short*>(smem), acc);
+    pipe_emit(sp, acc, f);
+  }
+}
+
+// Dynamic LDS bytes of either engine.
+template <int WR, int WC, int RT, int CT, int PC, int BK = 16>
+constexpr size_t pipe_lds_bytes() {
+  if constexpr (PC == 0) return Pipe<WR, WC, RT, CT, BK>::LDS_BYTES;
+  else return PipeMx<WR, WC, RT, CT, PC>::LDS_BYTES;
+}

@@ -22,6 +22,7 @@ struct SysDev {
   double* lbar = nullptr;     // [G]
   double* H1 = nullptr;       // [M][M]
   double* Bhalf = nullptr;    // [M][M] exp(-tau H1 / 2)
+  double* Bm1 = nullptr;      // [M][M] exp(-tau H1 / 2) - I (expm1 form)
   double tau_b = -1.0;
   double e_const = 0.0, e_trial = 0.0;
   std::vector<double> h1_evals, h1_evecs;   // host eigendecomposition of H1
@@ -64,6 +65,9 @@ struct SysDev {
   int64_t Lxb_ps = 0;
   unsigned short* thb = nullptr;  // [P][W 2N][Kp] pieces of Theta
   int64_t thb_ps = 0;
+  // BF16 pieces of the operator build, the one-body half-steps and the
+  // operator-orbital products of the current propagate call (0 = FP64)
+  int op_pieces = 0;
   // tuned tile shape of the local-energy contraction (0 = occupancy model)
   int x_ga = 0, x_wb = 0;
   // tuned column blocks of the operator-orbital product (0 = default)

@@ -161,21 +161,33 @@ afq_status check_symmetric(afq_ctx* ctx, const double* X, int64_t nb, int n, con
   return AFQ_OK;
 }
 
-// exp(-tau H1 / 2) from the host eigendecomposition.
+// exp(-tau H1 / 2) from the host eigendecomposition, and B - I formed with
+// expm1 (the correction the BF16-split half-step contracts, added to the
+// FP64 orbitals, so that its rounding acts on the small part only).
 afq_status ensure_half_step(afq_ctx* ctx, SysDev& s, double tau) {
-  if (s.tau_b == tau && s.Bhalf) return AFQ_OK;
+  if (s.tau_b == tau && s.Bhalf && s.Bm1) return AFQ_OK;
   const int M = s.M;
-  std::vector<double> d(M), B((size_t)M * M, 0.0);
-  for (int k = 0; k < M; ++k) d[k] = std::exp(-0.5 * tau * s.h1_evals[k]);
+  std::vector<double> d(M), dm(M), B((size_t)M * M, 0.0), Bm((size_t)M * M, 0.0);
+  for (int k = 0; k < M; ++k) {
+    d[k] = std::exp(-0.5 * tau * s.h1_evals[k]);
+    dm[k] = std::expm1(-0.5 * tau * s.h1_evals[k]);
+  }
   const double* V = s.h1_evecs.data();
   for (int p = 0; p < M; ++p)
     for (int q = p; q < M; ++q) {
-      double acc = 0.0;
-      for (int k = 0; k < M; ++k) acc += V[(size_t)p * M + k] * d[k] * V[(size_t)q * M + k];
+      double acc = 0.0, am = 0.0;
+      for (int k = 0; k < M; ++k) {
+        const double vv = V[(size_t)p * M + k] * V[(size_t)q * M + k];
+        acc += vv * d[k];
+        am += vv * dm[k];
+      }
       B[(size_t)p * M + q] = acc;
       B[(size_t)q * M + p] = acc;
+      Bm[(size_t)p * M + q] = am;
+      Bm[(size_t)q * M + p] = am;
     }
   HIPCHK(hipMemcpy(s.Bhalf, B.data(), sizeof(double) * M * M, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s.Bm1, Bm.data(), sizeof(double) * M * M, hipMemcpyHostToDevice));
   s.tau_b = tau;
   return AFQ_OK;
 }
@@ -279,6 +291,16 @@ struct Phase {
   }
 };
 
+// BF16 pieces of the local-energy contraction and of the propagation
+// contractions (operator build, half-steps, operator-orbital products) for a
+// precision mode; 0 = FP64.
+int energy_pieces(int prec) {
+  return prec == AFQ_PREC_FP64 ? 0 : prec == AFQ_PREC_MIXED_FAST ? 2 : 3;
+}
+int op_pieces_of(int prec) {
+  return prec == AFQ_PREC_MIXED ? 3 : prec == AFQ_PREC_MIXED_FAST ? 2 : 0;
+}
+
 // E0 of a system for a propagate call: the call's value, or the trial energy.
 double e0_of(const SysDev& s, const afq_prop_params& P) {
   return std::isnan(P.e0) ? s.e_trial : P.e0;
@@ -360,7 +382,7 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
 // Local-energy contraction of one system (FP64 or BF16-split).
 afq_status step_exchange(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, hipStream_t st) {
   Phase ph(ctx, AFQ_PH_EXCHANGE);
-  if (P.precision == AFQ_PREC_FP64) {
+  if (energy_pieces(P.precision) == 0) {
     HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
   } else {
     HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps, s.thb,
@@ -528,7 +550,7 @@ afq_status batch_step(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev
     HIPCHK(hipEventRecord(ctx->ev_join[b], ctx->br[b]));
     HIPCHK(hipStreamWaitEvent(origin, ctx->ev_join[b], 0));
   }
-  if (P.precision == AFQ_PREC_FP64) {
+  if (energy_pieces(P.precision) == 0) {
     afq_ctx::XTable* tab;
     TRY(get_xtable(ctx, ss, &tab));
     for (size_t c = 0; c < tab->ct.size(); ++c)
@@ -573,7 +595,7 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
         std::swap(s->th_re, s->thn_re);
         std::swap(s->th_im, s->thn_im);
       }
-      if (P.precision == AFQ_PREC_FP64) {
+      if (energy_pieces(P.precision) == 0) {
         afq_ctx::XTable* tab;
         afq_status r = get_xtable(ctx, ss, &tab);
         if (r != AFQ_OK) {
@@ -770,6 +792,7 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
   TRY(dalloc(ctx, own, &s.lbar, (size_t)G));
   TRY(dalloc(ctx, own, &s.H1, MM));
   TRY(dalloc(ctx, own, &s.Bhalf, MM));
+  TRY(dalloc(ctx, own, &s.Bm1, MM));
   HIPCHK(hipMemcpy(s.psit, pt.data(), pt.size() * 8, hipMemcpyHostToDevice));
   // Psi_T^T L_g for every g, and Psi_T^T h in the last block
   GemmArgs g{};
@@ -929,8 +952,7 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   if (P->exp_method != AFQ_EXP_KRYLOV && P->exp_method != AFQ_EXP_TAYLOR)
     return fail(ctx, AFQ_EINVAL, "unknown exp_method");
   if (P->exp_order < 1 || P->exp_order > 16) return fail(ctx, AFQ_EINVAL, "exp_order must be in [1, 16]");
-  if (P->precision != AFQ_PREC_FP64 && P->precision != AFQ_PREC_MIXED &&
-      P->precision != AFQ_PREC_MIXED_FAST)
+  if (P->precision < AFQ_PREC_FP64 || P->precision > AFQ_PREC_MIXED_ENERGY)
     return fail(ctx, AFQ_EINVAL, "unknown precision");
   if (P->n_steps < 0) return fail(ctx, AFQ_EINVAL, "n_steps < 0");
   if (P->fields && n_sys != 1) return fail(ctx, AFQ_EINVAL, "explicit fields need a single system");
@@ -959,8 +981,9 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
       return fail(ctx, AFQ_EINVAL, "Krylov path supports M <= 512");
     TRY(ensure_half_step(ctx, *ss[i], P->tau));
     if (P->exp_method == AFQ_EXP_KRYLOV) TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
-    if (P->precision != AFQ_PREC_FP64)
-      TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], P->precision == AFQ_PREC_MIXED ? 3 : 2));
+    if (energy_pieces(P->precision))
+      TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], energy_pieces(P->precision)));
+    ss[i]->op_pieces = op_pieces_of(P->precision);
     HIPCHK(hipMemsetAsync(ss[i]->counters, 0, 4 * sizeof(int), ctx->stream));
   }
   if (mode == AFQ_SCHED_SERIAL) {
@@ -1075,13 +1098,13 @@ afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precisio
   SysDev& s = *sp;
   if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
   if (!eloc_out) return fail(ctx, AFQ_EINVAL, "null eloc_out");
-  if (precision < AFQ_PREC_FP64 || precision > AFQ_PREC_MIXED_FAST)
+  if (precision < AFQ_PREC_FP64 || precision > AFQ_PREC_MIXED_ENERGY)
     return fail(ctx, AFQ_EINVAL, "unknown precision");
   HIPCHK(hipSetDevice(ctx->device));
-  if (precision == AFQ_PREC_FP64) {
+  if (energy_pieces(precision) == 0) {
     TRY(eval_energy(ctx, s, 0.0, 0.0));
   } else {
-    TRY(ensure_mixed(ctx, sys_id, s, precision == AFQ_PREC_MIXED ? 3 : 2));
+    TRY(ensure_mixed(ctx, sys_id, s, energy_pieces(precision)));
     HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps, s.thb,
                               ctx->stream));
     HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im,

@@ -121,6 +121,7 @@ __global__ __launch_bounds__(GPP::NT) void k_gemm_pipe(GemmArgs g, int nct) {
 
 using OBP = Pipe<4, 2, 2, 5>;
 
+template <int PC>
 __global__ __launch_bounds__(OBP::NT) void k_onebody(int WN, int M, int n_ct,
                                                      const double* __restrict__ in_re,
                                                      const double* __restrict__ in_im,
@@ -137,69 +138,62 @@ __global__ __launch_bounds__(OBP::NT) void k_onebody(int WN, int M, int n_ct,
     return rr < WN ? in_re[rr * M + k] : in_im[(rr - WN) * M + k];
   };
   auto gb = [&](int c, int k) { return Bm[(int64_t)(c0 + c) * M + k]; };
-  d4_t acc[2][5];
-  const PipeSplit sp = pipe_gemm<4, 2, 2, 5, false, false>(M, nr, nc, ga, gb, smem, acc);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      if (i >= sp.mtv || j >= sp.ntv) continue;
-      const int c = pipe_col(sp, j);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = pipe_row(sp, i, e);
-        if (r < nr && c < nc) {
-          const int64_t rr = r0 + r;
-          if (rr < WN) out_re[rr * M + c0 + c] = acc[i][j][e];
-          else out_im[(rr - WN) * M + c0 + c] = acc[i][j][e];
-        }
+  // FP64: Bm = B.  BF16-split: Bm = B - I and the FP64 input is added back.
+  pipe_run<4, 2, 2, 5, PC, false, false>(M, nr, nc, ga, gb, smem, [&](int r, int c, double v) {
+    if (r < nr && c < nc) {
+      const int64_t rr = r0 + r;
+      if (rr < WN) {
+        if (PC) v += in_re[rr * M + c0 + c];
+        out_re[rr * M + c0 + c] = v;
+      } else {
+        if (PC) v += in_im[(rr - WN) * M + c0 + c];
+        out_im[(rr - WN) * M + c0 + c] = v;
       }
     }
+  });
 }
 
 // ------------------------------------------------------------ operator build
 // A_plane[w][pq] = sum_g a_plane[w][g] L[g][pq],  a = i sqrt(tau) (x - fbar)
 
-using OPP = Pipe<4, 2, 2, 4>;
 
-__global__ __launch_bounds__(OPP::NT) void k_opbuild(int W, int G, int64_t MM,
+// Tile of the operator build for each engine (the BF16-split engine stages
+// four-k units and holds more fragments, so it takes a narrower tile).
+template <int PC>
+struct OpTile {
+  static constexpr int WR = 4, WC = 2, RT = 2, CT = PC == 0 ? 4 : 2;
+  static constexpr int ROWS = WR * RT * 16, COLS = WC * CT * 16, NT = WR * WC * 64;
+};
+
+template <int PC>
+__global__ __launch_bounds__(OpTile<PC>::NT) void k_opbuild(int W, int G, int64_t MM,
                                                      const double* __restrict__ a_re,
                                                      const double* __restrict__ a_im,
                                                      const double* __restrict__ L,
                                                      double* __restrict__ A_re,
                                                      double* __restrict__ A_im, int n_rt,
                                                      int n_ct) {
+  using T = OpTile<PC>;
   extern __shared__ double smem[];
   int ct, rt;
   if (!xcd_swizzle(blockIdx.x, n_rt, n_ct, ct, rt)) return;
-  const int r0 = rt * OPP::ROWS;
-  const int64_t c0 = (int64_t)ct * OPP::COLS;
+  const int r0 = rt * T::ROWS;
+  const int64_t c0 = (int64_t)ct * T::COLS;
   const int R = 2 * W;
-  const int nr = min(OPP::ROWS, R - r0);
-  const int nc = (int)min((int64_t)OPP::COLS, MM - c0);
+  const int nr = min(T::ROWS, R - r0);
+  const int nc = (int)min((int64_t)T::COLS, MM - c0);
   auto ga = [&](int r, int k) {
     const int rr = r0 + r;
     return rr < W ? a_re[(int64_t)rr * G + k] : a_im[(int64_t)(rr - W) * G + k];
   };
   auto gb = [&](int c, int k) { return L[(int64_t)k * MM + c0 + c]; };
-  d4_t acc[2][4];
-  const PipeSplit sp = pipe_gemm<4, 2, 2, 4, false, true>(G, nr, nc, ga, gb, smem, acc);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (i >= sp.mtv || j >= sp.ntv) continue;
-      const int c = pipe_col(sp, j);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = pipe_row(sp, i, e);
-        if (r < nr && c < nc) {
-          const int rr = r0 + r;
-          if (rr < W) A_re[(int64_t)rr * MM + c0 + c] = acc[i][j][e];
-          else A_im[(int64_t)(rr - W) * MM + c0 + c] = acc[i][j][e];
-        }
-      }
+  pipe_run<T::WR, T::WC, T::RT, T::CT, PC, false, true>(G, nr, nc, ga, gb, smem, [&](int r, int c, double v) {
+    if (r < nr && c < nc) {
+      const int rr = r0 + r;
+      if (rr < W) A_re[(int64_t)rr * MM + c0 + c] = v;
+      else A_im[(int64_t)(rr - W) * MM + c0 + c] = v;
     }
+  });
 }
 
 // ------------------------------------------------------------ A^w psi
@@ -225,7 +219,7 @@ struct VecOut {
   int64_t sw, sj;
 };
 
-template <int RT>
+template <int RT, int PC>
 __global__ __launch_bounds__(64 * MV_WR * MV_WC) void k_matvec(int W, int N, int M, VecRef v,
                                                        const double* __restrict__ A_re,
                                                        const double* __restrict__ A_im, VecOut o,
@@ -257,23 +251,12 @@ __global__ __launch_bounds__(64 * MV_WR * MV_WC) void k_matvec(int W, int N, int
     const int64_t p = c0 + c;
     return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
   };
-  d4_t acc[RT][MV_CT];
-  const PipeSplit sp =
-      pipe_gemm<MV_WR, MV_WC, RT, MV_CT, false, false, MV_BK>(2 * M, nr, nc, ga, gb, smem, acc);
-#pragma unroll
-  for (int i = 0; i < RT; ++i)
-#pragma unroll
-    for (int jt = 0; jt < MV_CT; ++jt) {
-      if (i >= sp.mtv || jt >= sp.ntv) continue;
-      const int c = pipe_col(sp, jt);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = pipe_row(sp, i, e);
+  pipe_run<MV_WR, MV_WC, RT, MV_CT, PC, false, false, MV_BK>(
+      2 * M, nr, nc, ga, gb, smem, [&](int r, int c, double val) {
         if (r < nr && c < nc) {
           const bool im_row = r >= N;
           const int j = im_row ? r - N : r;
           const int64_t off = (int64_t)w * o.sw + (int64_t)j * o.sj + c0 + c;
-          double val = acc[i][jt][e];
           if (mode == 1) {
             val *= inv_n;
             const int64_t soff = (int64_t)w * sum.sw + (int64_t)j * sum.sj + c0 + c;
@@ -283,8 +266,7 @@ __global__ __launch_bounds__(64 * MV_WR * MV_WC) void k_matvec(int W, int N, int
           if (im_row) o.im[off] = val;
           else o.re[off] = val;
         }
-      }
-    }
+      });
 }
 
 int matvec_col_blocks(int M) {
@@ -294,31 +276,40 @@ int matvec_col_blocks(int M) {
 }
 static_assert(MV_WR * MV_WC * 64 <= 1024, "workgroup size");
 
-template <int RT>
+template <int RT, int PC>
 hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                      hipStream_t st) {
-  using P = Pipe<MV_WR, MV_WC, RT, MV_CT, MV_BK>;
+  constexpr size_t lds = pipe_lds_bytes<MV_WR, MV_WC, RT, MV_CT, PC, MV_BK>();
   static bool lds_ok = false;
   if (!lds_ok) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT>,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT, PC>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     lds_ok = true;
   }
   const int n_ct = s.mv_ct > 0 ? s.mv_ct : matvec_col_blocks(s.M);
-  hipLaunchKernelGGL(k_matvec<RT>, dim3(xcd_grid(s.W, n_ct)), dim3(P::NT), P::LDS_BYTES, st, s.W,
-                     s.N, s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
+  hipLaunchKernelGGL((k_matvec<RT, PC>), dim3(xcd_grid(s.W, n_ct)), dim3(64 * MV_WR * MV_WC), lds,
+                     st, s.W, s.N, s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
   return hipGetLastError();
 }
 
-hipError_t run_matvec(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
-                      hipStream_t st) {
+template <int PC>
+hipError_t run_matvec_p(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+                        hipStream_t st) {
   const int TR = (2 * s.N + 15) / 16;
   const int rpw = (TR + MV_WR - 1) / MV_WR;
-  if (rpw <= 4) return matvec_rt<4>(s, v, o, mode, inv_n, sum, st);
-  if (rpw <= 7) return matvec_rt<7>(s, v, o, mode, inv_n, sum, st);
-  if (rpw <= 10) return matvec_rt<10>(s, v, o, mode, inv_n, sum, st);
+  if (rpw <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
+  if (rpw <= 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
+  if (rpw <= 10) return matvec_rt<10, PC>(s, v, o, mode, inv_n, sum, st);
   return hipErrorInvalidValue;
+}
+
+// The operator-orbital product in the system's current precision.
+hipError_t run_matvec(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+                      hipStream_t st) {
+  if (s.op_pieces == 3) return run_matvec_p<3>(s, v, o, mode, inv_n, sum, st);
+  if (s.op_pieces == 2) return run_matvec_p<2>(s, v, o, mode, inv_n, sum, st);
+  return run_matvec_p<0>(s, v, o, mode, inv_n, sum, st);
 }
 
 // ------------------------------------------------------------ Krylov pieces
@@ -584,11 +575,15 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
-                          double* out_im, hipStream_t st) {
+namespace {
+
+template <int PC>
+hipError_t onebody_p(SysDev& s, const double* in_re, const double* in_im, double* out_re,
+                     double* out_im, hipStream_t st) {
+  constexpr size_t lds = pipe_lds_bytes<4, 2, 2, 5, PC>();
   static bool lds_ok = false;
   if (!lds_ok) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_onebody,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_onebody<PC>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     lds_ok = true;
@@ -596,25 +591,43 @@ hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, d
   const int WN = s.W * s.N;
   const int nrt = (2 * WN + OBP::ROWS - 1) / OBP::ROWS;
   const int nct = (s.M + OBP::COLS - 1) / OBP::COLS;
-  hipLaunchKernelGGL(k_onebody, dim3(nrt * nct), dim3(OBP::NT), OBP::LDS_BYTES, st, WN, s.M, nct,
-                     in_re, in_im, s.Bhalf, out_re, out_im);
+  hipLaunchKernelGGL(k_onebody<PC>, dim3(nrt * nct), dim3(OBP::NT), lds, st, WN, s.M, nct, in_re,
+                     in_im, PC ? s.Bm1 : s.Bhalf, out_re, out_im);
   return hipGetLastError();
 }
 
-hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
+template <int PC>
+hipError_t opbuild_p(SysDev& s, hipStream_t st) {
+  using T = OpTile<PC>;
+  constexpr size_t lds = pipe_lds_bytes<T::WR, T::WC, T::RT, T::CT, PC>();
   static bool lds_ok = false;
   if (!lds_ok) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild<PC>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     lds_ok = true;
   }
   const int64_t MM = (int64_t)s.M * s.M;
-  const int n_rt = (2 * s.W + OPP::ROWS - 1) / OPP::ROWS;
-  const int n_ct = (int)((MM + OPP::COLS - 1) / OPP::COLS);
-  hipLaunchKernelGGL(k_opbuild, dim3(xcd_grid(n_ct, n_rt)), dim3(OPP::NT), OPP::LDS_BYTES, st, s.W,
-                     s.G, MM, s.av_re, s.av_im, s.L, s.A_re, s.A_im, n_rt, n_ct);
+  const int n_rt = (2 * s.W + T::ROWS - 1) / T::ROWS;
+  const int n_ct = (int)((MM + T::COLS - 1) / T::COLS);
+  hipLaunchKernelGGL(k_opbuild<PC>, dim3(xcd_grid(n_ct, n_rt)), dim3(T::NT), lds, st, s.W, s.G,
+                     MM, s.av_re, s.av_im, s.L, s.A_re, s.A_im, n_rt, n_ct);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
+                          double* out_im, hipStream_t st) {
+  if (s.op_pieces == 3) return onebody_p<3>(s, in_re, in_im, out_re, out_im, st);
+  if (s.op_pieces == 2) return onebody_p<2>(s, in_re, in_im, out_re, out_im, st);
+  return onebody_p<0>(s, in_re, in_im, out_re, out_im, st);
+}
+
+hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
+  if (s.op_pieces == 3) return opbuild_p<3>(s, st);
+  if (s.op_pieces == 2) return opbuild_p<2>(s, st);
+  return opbuild_p<0>(s, st);
 }
 
 hipError_t launch_taylor(SysDev& s, int k, const double* in_re, const double* in_im,
