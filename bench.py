@@ -26,6 +26,14 @@ sys.path.insert(0, ROOT)
 import afq_workloads as W  # noqa: E402
 
 PEAK_FP64 = 78.6e12          # MI355X dense FP64 matrix peak, flop/s
+PEAK_BF16 = 2.5e15           # MI355X dense BF16 matrix peak, flop/s
+PRECISIONS = {"fp64": lambda a: a.PREC_FP64, "mixed": lambda a: a.PREC_MIXED,
+              "mixed_fast": lambda a: a.PREC_MIXED_FAST,
+              "mixed_energy": lambda a: a.PREC_MIXED_ENERGY}
+DTYPES = {"fp64": "f64",
+          "mixed": "bf16x3 split, f32 accumulate (contractions); f64 elsewhere",
+          "mixed_fast": "bf16x2 split, f32 accumulate (contractions); f64 elsewhere",
+          "mixed_energy": "bf16x3 split, f32 accumulate (local energy); f64 elsewhere"}
 PEAK_HBM = 8.0e12            # bytes/s
 
 
@@ -393,6 +401,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "mixed", "mixed_fast", "mixed_energy"])
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="with --precision fp64: skip the mixed-precision runs beside it")
     ap.add_argument("--cpu-procs", type=int, default=None,
                     help="oracle processes for the CPU baseline (default: host cores, <= 16)")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -450,48 +460,72 @@ def main():
     sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
     ctx.init_trial(sid, psi)
     ctx.init_walkers(sid, cfg.W)
-    prec = {"fp64": afq.PREC_FP64, "mixed": afq.PREC_MIXED, "mixed_fast": afq.PREC_MIXED_FAST,
-            "mixed_energy": afq.PREC_MIXED_ENERGY}[args.precision]
-    kw = dict(tau=cfg.tau, exp_method=afq.EXP_KRYLOV, exp_order=cfg.k,
-              reorth_every=cfg.reorth_every, seed=0, precision=prec)
-    energies = torch.zeros((1, args.steps, 2), dtype=torch.float64, device="cuda")
-    log(f"warm-up: {args.warmup} steps")
-    ctx.propagate_batch(sid, n_steps=args.warmup, step0=0, **kw)
-    ctx.sync()
-    log(f"timed: {args.steps} steps")
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.propagate_batch(sid, n_steps=args.steps, step0=args.warmup, energies_out=energies, **kw)
-    ctx.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    dt = t1 - t0
-    ms_per_step = 1e3 * dt / args.steps
-    value = cfg.W * args.steps / dt
+    step0 = 0
+
+    def run_mode(name):
+        """Warm-up then timed steps in one precision mode (HIP-event phases)."""
+        nonlocal step0
+        prec = PRECISIONS[name](afq)
+        kw = dict(tau=cfg.tau, exp_method=afq.EXP_KRYLOV, exp_order=cfg.k,
+                  reorth_every=cfg.reorth_every, seed=0, precision=prec)
+        energies = torch.zeros((1, args.steps, 2), dtype=torch.float64, device="cuda")
+        log(f"{name}: warm-up {args.warmup} steps")
+        ctx.propagate_batch(sid, n_steps=args.warmup, step0=step0, **kw)
+        ctx.sync()
+        log(f"{name}: timed {args.steps} steps")
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.propagate_batch(sid, n_steps=args.steps, step0=step0 + args.warmup,
+                            energies_out=energies, **kw)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        step0 += args.warmup + args.steps
+        dt = t1 - t0
+        est = energies.cpu().numpy()[0]
+        ex_ms, ex_n = prof["exchange"]
+        ex_flops = exchange_flops_per_walker(cfg.M, cfg.N, cfg.G) * cfg.W
+        ex_avg_s = ex_ms / max(1, ex_n) / 1e3
+        if name == "fp64":
+            # FP64 matrix cores: the algorithmic flops against the FP64 peak
+            achieved, peak, kernel, fl = ex_flops / ex_avg_s, PEAK_FP64, "k_exchange", ex_flops
+        else:
+            # BF16 matrix cores: each FP64-equivalent product is 6 (3 pieces)
+            # or 3 (2 pieces) BF16 piece products, against the BF16 peak
+            prods = 3 if name == "mixed_fast" else 6
+            fl = prods * ex_flops
+            achieved, peak, kernel = fl / ex_avg_s, PEAK_BF16, "k_exchange_mx"
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(cfg, name), "kernel": kernel,
+                "avg_launch_ms": ex_avg_s * 1e3, "flops_per_launch": fl}
+        return {"value": cfg.W * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                "roofline": roof,
+                "phases": {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]}
+                           for k, v in prof.items()},
+                "energy_last_step": float(est[-1, 0] / est[-1, 1]) if est[-1, 1] else float("nan")}
+
+    main_run = run_mode(args.precision)
     cnt = ctx.get_counters(sid)
-    est = energies.cpu().numpy()[0]
-    e_last = float(est[-1, 0] / est[-1, 1]) if est[-1, 1] != 0 else float("nan")
-
-    ex_ms, ex_n = prof["exchange"]
-    ex_flops = exchange_flops_per_walker(cfg.M, cfg.N, cfg.G) * cfg.W
-    ex_avg_s = ex_ms / max(1, ex_n) / 1e3
-    achieved = ex_flops / ex_avg_s if ex_avg_s > 0 else 0.0
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-                "traffic": measured_traffic(cfg, args.precision),
-                "kernel": "k_exchange", "avg_launch_ms": ex_avg_s * 1e3,
-                "flops_per_launch": ex_flops}
+    others = {}
+    if args.precision == "fp64" and not args.no_mixed:
+        for name in ("mixed_energy", "mixed"):
+            r = run_mode(name)
+            others[name] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                            "speedup_vs_fp64": r["value"] / main_run["value"],
+                            "roofline": r["roofline"],
+                            "phases_ms_per_step": {k: v["ms_per_step"]
+                                                   for k, v in r["phases"].items()}}
+    ms_per_step = main_run["ms_per_step"]
     step_fl = step_flops_per_walker(cfg.M, cfg.N, cfg.G, cfg.k, cfg.reorth_every) * cfg.W
-    phases = {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]} for k, v in prof.items()}
-
     out = {
         "metric": "walker-steps/sec at M=300 (FP64 GPU; mixed and CPU oracle alongside)",
-        "value": value,
+        "value": main_run["value"],
         "unit": "walker-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -500,18 +534,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic (seeded random Cholesky Hamiltonian, mean-field trial, Philox fields)",
         "config": {"workload": f"{cfg.name}: M={cfg.M} N={cfg.N} G={cfg.G} walkers={cfg.W} "
                                f"Krylov k={cfg.k} QR every {cfg.reorth_every} tau={cfg.tau}",
                    "M": cfg.M, "N": cfg.N, "n_chol": cfg.G, "walkers": cfg.W, "k": cfg.k,
-                   "tau": cfg.tau, "reorth_every": cfg.reorth_every, "parallelism": "1 GPU"},
+                   "tau": cfg.tau, "reorth_every": cfg.reorth_every,
+                   "precision": args.precision, "parallelism": "1 GPU"},
         "step_tflops": step_fl / (ms_per_step / 1e3) / 1e12,
         "step_frac_fp64_peak": step_fl / (ms_per_step / 1e3) / PEAK_FP64,
-        "roofline": roofline,
-        "phases": phases,
+        "roofline": main_run["roofline"],
+        "phases": main_run["phases"],
         "counters": cnt,
-        "energy_last_step": e_last,
+        "energy_last_step": main_run["energy_last_step"],
+        "mixed": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
