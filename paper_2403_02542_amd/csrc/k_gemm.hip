@@ -203,10 +203,16 @@ __global__ __launch_bounds__(OpTile<PC>::NT) void k_opbuild(int W, int G, int64_
 //   col p:       [ A_re[p][q],   A_im[p][q] ]
 // mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
 
-// Four waves side by side over the columns (p); every wave holds all row
-// tiles (2N rows, RT >= ceil(2N / 16)) and up to two column tiles; K runs in
-// chunks of 32 so that each fetch from HBM covers 8 MFMA k-steps.
-constexpr int MV_WR = 1, MV_WC = 4, MV_CT = 2, MV_BK = 32;
+// Eight waves: two rows of waves split the 2N rows (RT = ceil(TR / 2) row
+// tiles each) and four columns of waves hold up to two column tiles each;
+// K runs in chunks of 32 so that each fetch from HBM covers 8 MFMA k-steps.
+// (The BF16-split engine keeps the single row of four waves: its fragment
+// registers do not leave room for the split rows.)
+template <int PC>
+struct MvCfg {
+  static constexpr int WR = PC == 0 ? 2 : 1, WC = 4, CT = 2, BK = 32;
+  static constexpr int NT = 64 * WR * WC;
+};
 
 struct VecRef {
   const double* re;
@@ -220,7 +226,7 @@ struct VecOut {
 };
 
 template <int RT, int PC>
-__global__ __launch_bounds__(64 * MV_WR * MV_WC) void k_matvec(int W, int N, int M, VecRef v,
+__global__ __launch_bounds__(MvCfg<PC>::NT) void k_matvec(int W, int N, int M, VecRef v,
                                                        const double* __restrict__ A_re,
                                                        const double* __restrict__ A_im, VecOut o,
                                                        int mode, double inv_n, VecOut sum,
@@ -251,7 +257,8 @@ __global__ __launch_bounds__(64 * MV_WR * MV_WC) void k_matvec(int W, int N, int
     const int64_t p = c0 + c;
     return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
   };
-  pipe_run<MV_WR, MV_WC, RT, MV_CT, PC, false, false, MV_BK>(
+  using C = MvCfg<PC>;
+  pipe_run<C::WR, C::WC, RT, C::CT, PC, false, false, C::BK>(
       2 * M, nr, nc, ga, gb, smem, [&](int r, int c, double val) {
         if (r < nr && c < nc) {
           const bool im_row = r >= N;
@@ -271,15 +278,16 @@ __global__ __launch_bounds__(64 * MV_WR * MV_WC) void k_matvec(int W, int N, int
 
 int matvec_col_blocks(int M) {
   const int TC = (M + 15) / 16;
-  const int per = MV_WC * MV_CT;
+  const int per = MvCfg<0>::WC * MvCfg<0>::CT;   // same for both engines
   return (TC + per - 1) / per;
 }
-static_assert(MV_WR * MV_WC * 64 <= 1024, "workgroup size");
+static_assert(MvCfg<0>::WC * MvCfg<0>::CT == MvCfg<3>::WC * MvCfg<3>::CT, "column blocks");
 
 template <int RT, int PC>
 hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                      hipStream_t st) {
-  constexpr size_t lds = pipe_lds_bytes<MV_WR, MV_WC, RT, MV_CT, PC, MV_BK>();
+  using C = MvCfg<PC>;
+  constexpr size_t lds = pipe_lds_bytes<C::WR, C::WC, RT, C::CT, PC, C::BK>();
   static bool lds_ok = false;
   if (!lds_ok) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT, PC>,
@@ -288,7 +296,7 @@ hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecO
     lds_ok = true;
   }
   const int n_ct = s.mv_ct > 0 ? s.mv_ct : matvec_col_blocks(s.M);
-  hipLaunchKernelGGL((k_matvec<RT, PC>), dim3(xcd_grid(s.W, n_ct)), dim3(64 * MV_WR * MV_WC), lds,
+  hipLaunchKernelGGL((k_matvec<RT, PC>), dim3(xcd_grid(s.W, n_ct)), dim3(C::NT), lds,
                      st, s.W, s.N, s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
   return hipGetLastError();
 }
@@ -297,10 +305,16 @@ template <int PC>
 hipError_t run_matvec_p(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                         hipStream_t st) {
   const int TR = (2 * s.N + 15) / 16;
-  const int rpw = (TR + MV_WR - 1) / MV_WR;
-  if (rpw <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
-  if (rpw <= 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
-  if (rpw <= 10) return matvec_rt<10, PC>(s, v, o, mode, inv_n, sum, st);
+  const int rpw = (TR + MvCfg<PC>::WR - 1) / MvCfg<PC>::WR;
+  if constexpr (MvCfg<PC>::WR == 2) {
+    if (rpw <= 3) return matvec_rt<3, PC>(s, v, o, mode, inv_n, sum, st);
+    if (rpw <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
+    if (rpw <= 5) return matvec_rt<5, PC>(s, v, o, mode, inv_n, sum, st);
+  } else {
+    if (rpw <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
+    if (rpw <= 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
+    if (rpw <= 10) return matvec_rt<10, PC>(s, v, o, mode, inv_n, sum, st);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -140,7 +140,9 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
       const int u = tid + i * MT_;
       uint4 v = make_uint4(0, 0, 0, 0);
       if (u < UNITS) {
-        const int k8 = u & 3, rp = u >> 2, p = rp % P, c = rp / P;
+        // consecutive lanes walk k, then columns, within one piece plane
+        // (lanes of one LDS store then hit distinct banks)
+        const int k8 = u & 3, rp = u >> 2, p = rp / BROWS, c = rp - p * BROWS;
         if (c < nc) v = *(const uint4*)(tb + p * tb_ps + (b_row0 + c) * Kp + k0 + k8 * 8);
       }
       pf[i] = v;
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
     for (int i = 0; i < PFU; ++i) {
       const int u = tid + i * MT_;
       if (u < UNITS) {
-        const int k8 = u & 3, rp = u >> 2, p = rp % P, c = rp / P;
+        const int k8 = u & 3, rp = u >> 2, p = rp / BROWS, c = rp - p * BROWS;
         *(uint4*)(S + ((size_t)p * BROWS + c) * M_PITCH + k8 * 8) = pf[i];
       }
     }

@@ -26,7 +26,7 @@ def small_batch():
     return W.make_uneven_batch(SMALL)
 
 
-def _run(batch, schedule, alone=False, tune=False):
+def _run(batch, schedule, alone=False, tune=False, precision=0):
     import torch
     from paper_2403_02542_amd import afq
     ctx = afq.Context(0)
@@ -41,7 +41,7 @@ def _run(batch, schedule, alone=False, tune=False):
         ctx.autotune(ids)
     en = torch.zeros((n, SMALL.steps, 2), dtype=torch.float64, device="cuda")
     kw = dict(tau=SMALL.tau, n_steps=SMALL.steps, exp_method=afq.EXP_KRYLOV, exp_order=SMALL.k,
-              reorth_every=SMALL.reorth_every, seed=0, schedule=schedule)
+              reorth_every=SMALL.reorth_every, seed=0, schedule=schedule, precision=precision)
     if alone:
         for i, sid in enumerate(ids):
             ctx.propagate_batch(sid, energies_out=en[i:i + 1], **kw)
@@ -50,7 +50,7 @@ def _run(batch, schedule, alone=False, tune=False):
     ctx.sync()
     torch.cuda.synchronize()
     out = [ctx.get_walkers(sid) for sid in ids]
-    el = [ctx.local_energy_batch(sid) for sid in ids]
+    el = [ctx.local_energy_batch(sid, precision=precision) for sid in ids]
     e = en.cpu().numpy()
     ctx.close()
     return out, el, e
@@ -98,6 +98,22 @@ def test_autotuned_tiles_keep_results(small_batch):
         for key in ("phi", "weight", "log_ovlp", "alive"):
             assert np.array_equal(out[i][key], ref[i][key]), (i, key)
         assert np.array_equal(el[i], ref_el[i]), i
+
+
+@pytest.mark.parametrize("prec_name", ["MIXED", "MIXED_ENERGY"])
+def test_uneven_schedules_mixed_precision(small_batch, prec_name):
+    """The schedules give bitwise the same results in the mixed modes too
+    (the BF16-split contractions run per system in every schedule)."""
+    from paper_2403_02542_amd import afq
+    prec = getattr(afq, "PREC_" + prec_name)
+    ref, ref_el, ref_e = _run(small_batch, afq.SCHED_SERIAL, precision=prec)
+    for sched in (afq.SCHED_STREAMS, afq.SCHED_GRAPH):
+        out, el, e = _run(small_batch, sched, precision=prec)
+        assert np.array_equal(e, ref_e), sched
+        for i in range(len(out)):
+            for key in ("phi", "weight", "log_ovlp", "alive"):
+                assert np.array_equal(out[i][key], ref[i][key]), (sched, i, key)
+            assert np.array_equal(el[i], ref_el[i]), (sched, i)
 
 
 def test_schedule_argument_errors(small_batch):
