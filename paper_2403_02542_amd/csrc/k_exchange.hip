@@ -31,6 +31,12 @@ constexpr int X_CTMAX = 10;                // max column tiles (all waves): 2N <
 constexpr int X_ROWS = XW * X_RT * 16;     // 256
 constexpr int X_COLS = X_CTMAX * 16;       // 160
 constexpr int X_STAGE = (X_ROWS + X_COLS) * kLDK;   // LDS stage (doubles), largest CT
+// The workgroup takes the whole 160 KB of LDS (one workgroup per compute unit
+// anyway): two stages for the main loop, then as many staged g-blocks as fit
+// for the epilogue, with the partial sums at the end.
+constexpr int X_LDS = 160 * 1024 / 8;                // doubles
+constexpr int X_RED = 4 * XW * 32;                   // partial sums [gl][wave][4]
+static_assert(2 * X_STAGE <= X_LDS - X_RED, "LDS budget");
 constexpr int X_SUPER_G = 4, X_SUPER_W = 8;         // super-tile per XCD
 
 // CT: column tiles held by every wave (compile-time, >= ceil(WB 2N / 16)).
@@ -129,7 +135,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
 
   // ---- epilogue: per walker, groups of `grp` g-blocks staged in LDS
   double* Ts = smem;
-  double* red = smem + 2 * X_STAGE - 4 * XW * 32;  // partial sums [gl][wave][4]
+  double* red = smem + X_LDS - X_RED;  // partial sums [gl][wave][4]
   const int ldt = twoN + 1;
   for (int wl = 0; wl < wb; ++wl) {
     for (int gb = 0; gb < ga; gb += grp) {
@@ -152,11 +158,20 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
         }
       }
       __syncthreads();
-      for (int gl = 0; gl < gn; ++gl) {
+      // the g-blocks of the group are spread over the waves (wpg waves per
+      // block); each wave walks its share of the N x N block with an
+      // incremental (i, j) and leaves one partial sum per block
+      const int wpg = gn < XW ? XW / gn : 1;
+      const int slot = wave / wpg, sub = wave - slot * wpg;
+      const int nslot = XW / wpg;
+      const int step = wpg * 64;
+      const int dq = step / N, dr = step - dq * N;
+      for (int gl = slot; gl < gn && slot < nslot; gl += nslot) {
         const double* T = Ts + (int64_t)gl * N * ldt;
         double xr = 0.0, xi = 0.0, tr = 0.0, ti = 0.0;
-        for (int e = tid; e < N * N; e += XT) {
-          const int i = e / N, j = e - i * N;
+        const int e0 = sub * 64 + lane;
+        int i = e0 / N, j = e0 - (e0 / N) * N;
+        for (int e = e0; e < N * N; e += step) {
           const double ar = T[i * ldt + j], ai = T[i * ldt + N + j];
           const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
           xr += ar * br - ai * bi;
@@ -165,13 +180,19 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
             tr += ar;
             ti += ai;
           }
+          i += dq;
+          j += dr;
+          if (j >= N) {
+            j -= N;
+            ++i;
+          }
         }
         xr = wave_sum(xr);
         xi = wave_sum(xi);
         tr = wave_sum(tr);
         ti = wave_sum(ti);
         if (lane == 0) {
-          double* rr = red + (gl * XW + wave) * 4;
+          double* rr = red + (gl * XW + sub) * 4;
           rr[0] = xr;
           rr[1] = xi;
           rr[2] = tr;
@@ -181,7 +202,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
       __syncthreads();
       if (tid < gn) {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int v = 0; v < XW; ++v)
+        for (int v = 0; v < wpg; ++v)
           for (int q = 0; q < 4; ++q) s[q] += red[(tid * XW + v) * 4 + q];
         const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb + tid;
         ex_re[o] = s[0];
@@ -257,10 +278,8 @@ hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const dou
     WB = s.x_wb;
   }
   if (GA * N > X_ROWS || WB * 2 * N > X_COLS || (GA * N + 15) / 16 > XW * X_RT) return hipErrorInvalidValue;
-  // LDS: two stages; the epilogue reuses them for T (grp g-blocks at a time)
-  // and keeps the partial sums at the end.
-  const int red_d = 4 * XW * 32;
-  const int avail = 2 * X_STAGE - red_d;
+  // LDS: the epilogue stages grp g-blocks at a time.
+  const int avail = X_LDS - X_RED;
   int grp = avail / (N * (2 * N + 1));
   if (grp > 32) grp = 32;
   if (grp < 1) return hipErrorInvalidValue;
@@ -294,7 +313,7 @@ hipError_t run_exchange(const XSys& p, int n_gt, int n_wt, hipStream_t st) {
   const int n_sg = (n_gt + X_SUPER_G - 1) / X_SUPER_G;
   const int n_sw = (n_wt + X_SUPER_W - 1) / X_SUPER_W;
   const int grid = ((n_sg * n_sw + 7) / 8) * 8 * X_SUPER_G * X_SUPER_W;
-  hipLaunchKernelGGL(k_exchange<CT>, dim3(grid), dim3(XT), sizeof(double) * 2 * X_STAGE, st, p,
+  hipLaunchKernelGGL(k_exchange<CT>, dim3(grid), dim3(XT), sizeof(double) * X_LDS, st, p,
                      n_gt, n_wt);
   return hipGetLastError();
 }
@@ -303,7 +322,7 @@ template <int CT>
 hipError_t run_exchange_group(const XSys* d_sys, const int4* d_tiles, int n_tiles, hipStream_t st) {
   hipError_t e = allow_exchange_lds<CT>();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_exchange_group<CT>, dim3(n_tiles), dim3(XT), sizeof(double) * 2 * X_STAGE,
+  hipLaunchKernelGGL(k_exchange_group<CT>, dim3(n_tiles), dim3(XT), sizeof(double) * X_LDS,
                      st, d_sys, d_tiles);
   return hipGetLastError();
 }

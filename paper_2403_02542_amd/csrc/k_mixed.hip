@@ -206,7 +206,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
   }
 
   // ---- epilogue (as in the FP64 kernel), T in float64
-  double* Ts = smem;
+  float* Ts = (float*)smem;                    // T blocks in FP32 (their precision)
   double* red = smem + red_off;               // partial sums [gl][wave][4]
   const int ldt = twoN + 1;
   for (int wl = 0; wl < wb; ++wl) {
@@ -225,16 +225,25 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int r = (rt0 + i) * 16 + (lane >> 4) * 4 + e;
-            if (r >= rlo && r < rhi) Ts[(r - rlo) * ldt + c] = (double)acc[i][j][e];
+            if (r >= rlo && r < rhi) Ts[(r - rlo) * ldt + c] = acc[i][j][e];
           }
         }
       }
       __syncthreads();
-      for (int gl = 0; gl < gn; ++gl) {
-        const double* T = Ts + (int64_t)gl * N * ldt;
+      // the g-blocks of the group are spread over the waves (wpg waves per
+      // block); each wave walks its share of the N x N block with an
+      // incremental (i, j) and leaves one partial sum per block
+      const int wpg = gn < MW ? MW / gn : 1;
+      const int slot = wave / wpg, sub = wave - slot * wpg;
+      const int nslot = MW / wpg;
+      const int step = wpg * 64;
+      const int dq = step / N, dr = step - dq * N;
+      for (int gl = slot; gl < gn && slot < nslot; gl += nslot) {
+        const float* T = Ts + (int64_t)gl * N * ldt;
         double xr = 0.0, xi = 0.0, tr = 0.0, ti = 0.0;
-        for (int e = tid; e < N * N; e += MT_) {
-          const int i = e / N, j = e - i * N;
+        const int e0 = sub * 64 + lane;
+        int i = e0 / N, j = e0 - (e0 / N) * N;
+        for (int e = e0; e < N * N; e += step) {
           const double ar = T[i * ldt + j], ai = T[i * ldt + N + j];
           const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
           xr += ar * br - ai * bi;
@@ -243,13 +252,19 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
             tr += ar;
             ti += ai;
           }
+          i += dq;
+          j += dr;
+          if (j >= N) {
+            j -= N;
+            ++i;
+          }
         }
         xr = wave_sum(xr);
         xi = wave_sum(xi);
         tr = wave_sum(tr);
         ti = wave_sum(ti);
         if (lane == 0) {
-          double* rr = red + (gl * MW + wave) * 4;
+          double* rr = red + (gl * MW + sub) * 4;
           rr[0] = xr;
           rr[1] = xi;
           rr[2] = tr;
@@ -259,7 +274,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
       __syncthreads();
       if (tid < gn) {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int v = 0; v < MW; ++v)
+        for (int v = 0; v < wpg; ++v)
           for (int q = 0; q < 4; ++q) s[q] += red[(tid * MW + v) * 4 + q];
         const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb + tid;
         ex_re[o] = s[0];
@@ -299,14 +314,16 @@ hipError_t launch_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps, 
   const int n_sg = (n_gt + M_SUPER_G - 1) / M_SUPER_G;
   const int n_sw = (n_wt + M_SUPER_W - 1) / M_SUPER_W;
   const int grid = ((n_sg * n_sw + 7) / 8) * 8 * M_SUPER_G * M_SUPER_W;
-  // LDS: two B stages; the epilogue reuses it for T (grp blocks) + partials
+  // LDS: the whole 160 KB (one workgroup per compute unit): two B stages for
+  // the main loop, then as many FP32 T blocks as fit for the epilogue, with
+  // the partial sums at the end
   const int red_d = 4 * MW * 32;
   const size_t stage_doubles = ((size_t)2 * P * CT * 16 * M_PITCH * 2 + 7) / 8;
-  const size_t t_need = (size_t)N * (2 * N + 1) * 2 + red_d;   // at least two blocks
-  const size_t lds_doubles = stage_doubles > t_need ? stage_doubles : t_need;
-  int grp = (int)((lds_doubles - red_d) / ((size_t)N * (2 * N + 1)));
+  const size_t lds_doubles = 160 * 1024 / 8;
+  if (stage_doubles > lds_doubles - red_d) return hipErrorInvalidValue;
+  int grp = (int)((lds_doubles - red_d) * 2 / ((size_t)N * (2 * N + 1)));
   if (grp > 32) grp = 32;
-  if (grp < 1 || lds_doubles * 8 > 160 * 1024) return hipErrorInvalidValue;
+  if (grp < 1) return hipErrorInvalidValue;
   const int red_off = (int)(lds_doubles - red_d);
   static bool lds_ok = false;
   if (!lds_ok) {
