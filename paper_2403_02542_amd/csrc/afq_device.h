@@ -295,6 +295,7 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
   };
   const int nchunk = (K + BK - 1) / BK;
   const int lr = lane & 15, lk = lane >> 4;
+  const bool full = sp.mtv == RT && sp.ntv == CT;
   fetch(0);
   store(smem);
   __syncthreads();
@@ -302,21 +303,37 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
     const double* As = smem + (ch & 1) * P::STAGE;
     const double* Bs = As + P::ROWS * LDK;
     if (ch + 1 < nchunk) fetch((ch + 1) * BK);
+    if (full) {
+      // the wave holds RT x CT tiles: no per-MFMA conditions
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double a[RT], b[CT];
+      for (int kk = 0; kk < BK; kk += 4) {
+        double a[RT], b[CT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i)
-        a[i] = i < sp.mtv ? As[((sp.rt0 + i) * 16 + lr) * LDK + kk + lk] : 0.0;
+        for (int i = 0; i < RT; ++i) a[i] = As[((sp.rt0 + i) * 16 + lr) * LDK + kk + lk];
 #pragma unroll
-      for (int j = 0; j < CT; ++j)
-        b[j] = j < sp.ntv ? Bs[((sp.ct0 + j) * 16 + lr) * LDK + kk + lk] : 0.0;
+        for (int j = 0; j < CT; ++j) b[j] = Bs[((sp.ct0 + j) * 16 + lr) * LDK + kk + lk];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) {
-        if (i < sp.mtv) {
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
-          for (int j = 0; j < CT; ++j)
-            if (j < sp.ntv) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < CT; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double a[RT], b[CT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+          a[i] = i < sp.mtv ? As[((sp.rt0 + i) * 16 + lr) * LDK + kk + lk] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+          b[j] = j < sp.ntv ? Bs[((sp.ct0 + j) * 16 + lr) * LDK + kk + lk] : 0.0;
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          if (i < sp.mtv) {
+#pragma unroll
+            for (int j = 0; j < CT; ++j)
+              if (j < sp.ntv) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+          }
         }
       }
     }

@@ -104,6 +104,9 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
     for (int j = 0; j < CT; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
   const int nchunk = (M + kBK - 1) / kBK;
+  // (the widest instance keeps the generic loop: the unconditional copy would
+  // not fit its registers)
+  const bool full = CT < 10 && mtv == X_RT && TC == CT;
   const int lr = lane & 15, lk = lane >> 4;
   fetch(0);
   store(smem);
@@ -113,19 +116,36 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
     if (ch + 1 < nchunk) fetch((ch + 1) * kBK);
     const double* As = S;
     const double* Bs = S + X_ROWS * kLDK;
+    if (full) {
+      // every wave holds X_RT row tiles and the tile has CT column tiles: no
+      // per-MFMA conditions, so loads and MFMAs interleave freely
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 4) {
-      double a[X_RT], b[CT];
+      for (int kk = 0; kk < kBK; kk += 4) {
+        double a[X_RT], b[CT];
 #pragma unroll
-      for (int i = 0; i < X_RT; ++i) a[i] = As[((rt0 + i) * 16 + lr) * kLDK + kk + lk];
+        for (int i = 0; i < X_RT; ++i) a[i] = As[((rt0 + i) * 16 + lr) * kLDK + kk + lk];
 #pragma unroll
-      for (int j = 0; j < CT; ++j) b[j] = j < TC ? Bs[(j * 16 + lr) * kLDK + kk + lk] : 0.0;
+        for (int j = 0; j < CT; ++j) b[j] = Bs[(j * 16 + lr) * kLDK + kk + lk];
 #pragma unroll
-      for (int i = 0; i < X_RT; ++i) {
-        if (i < mtv) {
+        for (int i = 0; i < X_RT; ++i)
 #pragma unroll
-          for (int j = 0; j < CT; ++j)
-            if (j < TC) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < CT; ++j) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < kBK; kk += 4) {
+        double a[X_RT], b[CT];
+#pragma unroll
+        for (int i = 0; i < X_RT; ++i) a[i] = As[((rt0 + i) * 16 + lr) * kLDK + kk + lk];
+#pragma unroll
+        for (int j = 0; j < CT; ++j) b[j] = j < TC ? Bs[(j * 16 + lr) * kLDK + kk + lk] : 0.0;
+#pragma unroll
+        for (int i = 0; i < X_RT; ++i) {
+          if (i < mtv) {
+#pragma unroll
+            for (int j = 0; j < CT; ++j)
+              if (j < TC) acc[i][j] = mfma_f64(a[i], b[j], acc[i][j]);
+          }
         }
       }
     }

@@ -166,6 +166,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
     for (int j = 0; j < CT; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
   const int nchunk = Kp / M_KC;
+  const bool full = mtv == M_RT && TC == CT;
   fetch_a(0, afr);
   fetch_b(0);
   store_b(lds);
@@ -178,20 +179,38 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
       fetch_a((ch + 1) * M_KC, anx);
       fetch_b((ch + 1) * M_KC);
     }
+    if (full) {
+      // all row tiles and all CT column tiles present: no per-MFMA conditions
 #pragma unroll
-    for (int j = 0; j < CT; ++j) {
-      if (j >= TC) continue;
-      bf8_t b[P];
+      for (int j = 0; j < CT; ++j) {
+        bf8_t b[P];
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-        b[p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + j * 16 + lr) * M_PITCH + lk);
+        for (int p = 0; p < P; ++p)
+          b[p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + j * 16 + lr) * M_PITCH + lk);
 #pragma unroll
-      for (int i = 0; i < M_RT; ++i) {
-        if (i >= mtv) continue;
+        for (int i = 0; i < M_RT; ++i)
 #pragma unroll
-        for (int q = 0; q < MxProds<P>::N; ++q) {
-          const uint4 av = afr[i][MxProds<P>::a[q]];
-          acc[i][j] = mfma_bf16(*(const bf8_t*)&av, b[MxProds<P>::b[q]], acc[i][j]);
+          for (int q = 0; q < MxProds<P>::N; ++q) {
+            const uint4 av = afr[i][MxProds<P>::a[q]];
+            acc[i][j] = mfma_bf16(*(const bf8_t*)&av, b[MxProds<P>::b[q]], acc[i][j]);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        if (j >= TC) continue;
+        bf8_t b[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          b[p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + j * 16 + lr) * M_PITCH + lk);
+#pragma unroll
+        for (int i = 0; i < M_RT; ++i) {
+          if (i >= mtv) continue;
+#pragma unroll
+          for (int q = 0; q < MxProds<P>::N; ++q) {
+            const uint4 av = afr[i][MxProds<P>::a[q]];
+            acc[i][j] = mfma_bf16(*(const bf8_t*)&av, b[MxProds<P>::b[q]], acc[i][j]);
+          }
         }
       }
     }
