@@ -106,7 +106,9 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
   const int nchunk = (M + kBK - 1) / kBK;
   // (the widest instance keeps the generic loop: the unconditional copy would
   // not fit its registers)
-  const bool full = CT < 10 && mtv == X_RT && TC == CT;
+  // (column tiles TC..CT-1 of the stage hold zeros, so their MFMAs are wasted
+  // but harmless; the occupancy model prices them in)
+  const bool full = CT < 10 && mtv == X_RT;
   const int lr = lane & 15, lk = lane >> 4;
   fetch(0);
   store(smem);
@@ -117,8 +119,8 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
     const double* As = S;
     const double* Bs = S + X_ROWS * kLDK;
     if (full) {
-      // every wave holds X_RT row tiles and the tile has CT column tiles: no
-      // per-MFMA conditions, so loads and MFMAs interleave freely
+      // every wave holds X_RT row tiles: no per-MFMA conditions, so loads and
+      // MFMAs interleave freely
 #pragma unroll
       for (int kk = 0; kk < kBK; kk += 4) {
         double a[X_RT], b[CT];
@@ -157,6 +159,8 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
   double* Ts = smem;
   double* red = smem + X_LDS - X_RED;  // partial sums [gl][wave][4]
   const int ldt = twoN + 1;
+  const int ei0 = tid / N, ej0 = tid - ei0 * N;                  // element tid
+  const int edq = (XW * 64) / N, edr = XW * 64 - edq * N;     // advance per stride
   for (int wl = 0; wl < wb; ++wl) {
     for (int gb = 0; gb < ga; gb += grp) {
       const int gn = min(grp, ga - gb);
@@ -178,20 +182,15 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
         }
       }
       __syncthreads();
-      // the g-blocks of the group are spread over the waves (wpg waves per
-      // block); each wave walks its share of the N x N block with an
-      // incremental (i, j) and leaves one partial sum per block
-      const int wpg = gn < XW ? XW / gn : 1;
-      const int slot = wave / wpg, sub = wave - slot * wpg;
-      const int nslot = XW / wpg;
-      const int step = wpg * 64;
-      const int dq = step / N, dr = step - dq * N;
-      for (int gl = slot; gl < gn && slot < nslot; gl += nslot) {
+      // every g-block is cut the same way whatever the tile shape (wave w
+      // sums the elements e = w * 64 + lane (mod XW * 64) of the block), so the
+      // sums, and the results, do not depend on GA, WB or the group size; the
+      // (i, j) of an element advances incrementally
+      for (int gl = 0; gl < gn; ++gl) {
         const double* T = Ts + (int64_t)gl * N * ldt;
         double xr = 0.0, xi = 0.0, tr = 0.0, ti = 0.0;
-        const int e0 = sub * 64 + lane;
-        int i = e0 / N, j = e0 - (e0 / N) * N;
-        for (int e = e0; e < N * N; e += step) {
+        int i = ei0, j = ej0;
+        for (int e = tid; e < N * N; e += XW * 64) {
           const double ar = T[i * ldt + j], ai = T[i * ldt + N + j];
           const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
           xr += ar * br - ai * bi;
@@ -200,8 +199,8 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
             tr += ar;
             ti += ai;
           }
-          i += dq;
-          j += dr;
+          i += edq;
+          j += edr;
           if (j >= N) {
             j -= N;
             ++i;
@@ -212,7 +211,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
         tr = wave_sum(tr);
         ti = wave_sum(ti);
         if (lane == 0) {
-          double* rr = red + (gl * XW + sub) * 4;
+          double* rr = red + (gl * XW + wave) * 4;
           rr[0] = xr;
           rr[1] = xi;
           rr[2] = tr;
@@ -222,7 +221,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
       __syncthreads();
       if (tid < gn) {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int v = 0; v < wpg; ++v)
+        for (int v = 0; v < XW; ++v)
           for (int q = 0; q < 4; ++q) s[q] += red[(tid * XW + v) * 4 + q];
         const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb + tid;
         ex_re[o] = s[0];
@@ -264,6 +263,9 @@ __global__ __launch_bounds__(XT) void k_exchange_group(const XSys* __restrict__ 
 
 // Choose GA (g-blocks per tile) and WB (walkers per tile) for N: maximise
 // the useful fraction of the MFMA work of the busiest wave.
+// Column tiles of the kernel instance that serves TC.
+int exchange_ct(int TC) { return TC <= 4 ? 4 : TC <= 7 ? 7 : TC <= 8 ? 8 : 10; }
+
 void exchange_tile(int N, int& GA, int& WB) {
   double best = -1.0;
   GA = 1;
@@ -274,7 +276,7 @@ void exchange_tile(int N, int& GA, int& WB) {
       const int rpw = (TR + XW - 1) / XW;
       if (rpw > X_RT || TC > X_CTMAX) continue;
       const double useful = (double)ga * N * wb * 2 * N;
-      const double work = (double)XW * rpw * TC * 256.0;
+      const double work = (double)XW * rpw * exchange_ct(TC) * 256.0;
       const double eff = useful / work + 1e-6 * ga * wb;
       if (eff > best) {
         best = eff;
@@ -305,7 +307,7 @@ hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const dou
   if (grp < 1) return hipErrorInvalidValue;
   const int TC = (WB * 2 * N + 15) / 16;
   *p = XSys{s.Lx, th_re, th_im, ell_re, ell_im, ex_re, ex_im, G1, N, s.M, W, GA, WB, grp,
-            TC <= 4 ? 4 : TC <= 7 ? 7 : TC <= 8 ? 8 : 10};
+            exchange_ct(TC)};
   *n_gt = (G1 + GA - 1) / GA;
   *n_wt = (W + WB - 1) / WB;
   return hipSuccess;
@@ -401,7 +403,7 @@ void exchange_candidates(int N, std::vector<int2>& out) {
       const int rpw = (TR + XW - 1) / XW;
       if (rpw > X_RT || TC > X_CTMAX) continue;
       const double useful = (double)ga * N * wb * 2 * N;
-      const double work = (double)XW * rpw * TC * 256.0;
+      const double work = (double)XW * rpw * exchange_ct(TC) * 256.0;
       cs.push_back(C{useful / work + 1e-6 * ga * wb, ga, wb});
     }
   std::sort(cs.begin(), cs.end(), [](const C& a, const C& b) { return a.eff > b.eff; });

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
     for (int j = 0; j < CT; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
   const int nchunk = Kp / M_KC;
-  const bool full = mtv == M_RT && TC == CT;
+  const bool full = mtv == M_RT;   // column tiles TC..CT-1 of the stage are zeros
   fetch_a(0, afr);
   fetch_b(0);
   store_b(lds);
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
       fetch_b((ch + 1) * M_KC);
     }
     if (full) {
-      // all row tiles and all CT column tiles present: no per-MFMA conditions
+      // all row tiles present: no per-MFMA conditions
 #pragma unroll
       for (int j = 0; j < CT; ++j) {
         bf8_t b[P];
@@ -228,6 +228,8 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
   float* Ts = (float*)smem;                    // T blocks in FP32 (their precision)
   double* red = smem + red_off;               // partial sums [gl][wave][4]
   const int ldt = twoN + 1;
+  const int ei0 = tid / N, ej0 = tid - ei0 * N;                  // element tid
+  const int edq = (MW * 64) / N, edr = MW * 64 - edq * N;     // advance per stride
   for (int wl = 0; wl < wb; ++wl) {
     for (int gb = 0; gb < ga; gb += grp) {
       const int gn = min(grp, ga - gb);
@@ -249,20 +251,15 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
         }
       }
       __syncthreads();
-      // the g-blocks of the group are spread over the waves (wpg waves per
-      // block); each wave walks its share of the N x N block with an
-      // incremental (i, j) and leaves one partial sum per block
-      const int wpg = gn < MW ? MW / gn : 1;
-      const int slot = wave / wpg, sub = wave - slot * wpg;
-      const int nslot = MW / wpg;
-      const int step = wpg * 64;
-      const int dq = step / N, dr = step - dq * N;
-      for (int gl = slot; gl < gn && slot < nslot; gl += nslot) {
+      // every g-block is cut the same way whatever the tile shape (wave w
+      // sums the elements e = w * 64 + lane (mod MW * 64) of the block), so the
+      // sums, and the results, do not depend on GA, WB or the group size; the
+      // (i, j) of an element advances incrementally
+      for (int gl = 0; gl < gn; ++gl) {
         const float* T = Ts + (int64_t)gl * N * ldt;
         double xr = 0.0, xi = 0.0, tr = 0.0, ti = 0.0;
-        const int e0 = sub * 64 + lane;
-        int i = e0 / N, j = e0 - (e0 / N) * N;
-        for (int e = e0; e < N * N; e += step) {
+        int i = ei0, j = ej0;
+        for (int e = tid; e < N * N; e += MW * 64) {
           const double ar = T[i * ldt + j], ai = T[i * ldt + N + j];
           const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
           xr += ar * br - ai * bi;
@@ -271,8 +268,8 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
             tr += ar;
             ti += ai;
           }
-          i += dq;
-          j += dr;
+          i += edq;
+          j += edr;
           if (j >= N) {
             j -= N;
             ++i;
@@ -283,7 +280,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
         tr = wave_sum(tr);
         ti = wave_sum(ti);
         if (lane == 0) {
-          double* rr = red + (gl * MW + sub) * 4;
+          double* rr = red + (gl * MW + wave) * 4;
           rr[0] = xr;
           rr[1] = xi;
           rr[2] = tr;
@@ -293,7 +290,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
       __syncthreads();
       if (tid < gn) {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int v = 0; v < wpg; ++v)
+        for (int v = 0; v < MW; ++v)
           for (int q = 0; q < 4; ++q) s[q] += red[(tid * MW + v) * 4 + q];
         const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb + tid;
         ex_re[o] = s[0];
@@ -315,7 +312,8 @@ void exchange_mx_tile(int N, int& GA, int& WB) {
       const int rpw = (TR + MW - 1) / MW;
       if (rpw > M_RT || TC > 10) continue;
       const double useful = (double)ga * N * wb * 2 * N;
-      const double work = (double)MW * rpw * TC * 256.0;
+      const int ct = TC <= 4 ? 4 : TC <= 7 ? 7 : 10;   // width of the kernel instance
+      const double work = (double)MW * rpw * ct * 256.0;
       const double eff = useful / work + 1e-6 * ga * wb;
       if (eff > best) {
         best = eff;
