@@ -195,10 +195,6 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
           const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
           xr += ar * br - ai * bi;
           xi += ar * bi + ai * br;
-          if (i == j) {
-            tr += ar;
-            ti += ai;
-          }
           i += edq;
           j += edr;
           if (j >= N) {
@@ -208,8 +204,14 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
         }
         xr = wave_sum(xr);
         xi = wave_sum(xi);
-        tr = wave_sum(tr);
-        ti = wave_sum(ti);
+        if (wave == gl % XW) {   // one wave adds up the diagonal (tr T)
+          for (int d = lane; d < N; d += 64) {
+            tr += T[d * ldt + d];
+            ti += T[d * ldt + N + d];
+          }
+          tr = wave_sum(tr);
+          ti = wave_sum(ti);
+        }
         if (lane == 0) {
           double* rr = red + (gl * XW + wave) * 4;
           rr[0] = xr;

@@ -264,10 +264,6 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
           const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
           xr += ar * br - ai * bi;
           xi += ar * bi + ai * br;
-          if (i == j) {
-            tr += ar;
-            ti += ai;
-          }
           i += edq;
           j += edr;
           if (j >= N) {
@@ -277,8 +273,14 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
         }
         xr = wave_sum(xr);
         xi = wave_sum(xi);
-        tr = wave_sum(tr);
-        ti = wave_sum(ti);
+        if (wave == gl % MW) {   // one wave adds up the diagonal (tr T)
+          for (int d = lane; d < N; d += 64) {
+            tr += T[d * ldt + d];
+            ti += T[d * ldt + N + d];
+          }
+          tr = wave_sum(tr);
+          ti = wave_sum(ti);
+        }
         if (lane == 0) {
           double* rr = red + (gl * MW + wave) * 4;
           rr[0] = xr;
