@@ -55,6 +55,10 @@ constexpr int M_ROWS = MW * M_RT * 16;     // 256
 constexpr int M_KC = 32;                   // K per chunk (one MFMA k-step)
 constexpr int M_PITCH = 40;                // bf16 per staged row (32 + 8 pad)
 constexpr int M_SUPER_G = 4, M_SUPER_W = 8;
+// Up to 13 column tiles (208 columns): two walkers per tile up to N = 52, so
+// every row fragment loaded from HBM feeds both walkers' products.
+constexpr int M_CTMAX = 13;
+inline int mx_ct(int TC) { return TC <= 4 ? 4 : TC <= 7 ? 7 : TC <= 10 ? 10 : 13; }
 
 template <int P>
 struct MxProds;
@@ -309,12 +313,12 @@ void exchange_mx_tile(int N, int& GA, int& WB) {
   GA = 1;
   WB = 1;
   for (int ga = 1; ga * N <= M_ROWS; ++ga)
-    for (int wb = 1; wb * 2 * N <= 160; ++wb) {
+    for (int wb = 1; wb * 2 * N <= 16 * M_CTMAX; ++wb) {
       const int TR = (ga * N + 15) / 16, TC = (wb * 2 * N + 15) / 16;
       const int rpw = (TR + MW - 1) / MW;
-      if (rpw > M_RT || TC > 10) continue;
+      if (rpw > M_RT || TC > M_CTMAX) continue;
       const double useful = (double)ga * N * wb * 2 * N;
-      const int ct = TC <= 4 ? 4 : TC <= 7 ? 7 : 10;   // width of the kernel instance
+      const int ct = mx_ct(TC);   // width of the kernel instance
       const double work = (double)MW * rpw * ct * 256.0;
       const double eff = useful / work + 1e-6 * ga * wb;
       if (eff > best) {
@@ -385,9 +389,11 @@ hipError_t launch_exchange_mx(SysDev& s, int W, const unsigned short* tb, int64_
   if (s.mx_pieces == 3) {
     if (TC <= 4) return launch_mx<4, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
     if (TC <= 7) return launch_mx<7, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
-    return launch_mx<10, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+    if (TC <= 10) return launch_mx<10, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+    return launch_mx<13, 3>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
   }
   if (TC <= 4) return launch_mx<4, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
   if (TC <= 7) return launch_mx<7, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
-  return launch_mx<10, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+  if (TC <= 10) return launch_mx<10, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+  return launch_mx<13, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
 }
