@@ -500,6 +500,7 @@ AFQ_DEV PipeSplit pipe_gemm_mx(int K, int nr, int nc, GA ga, GB gb, unsigned sho
       }
     }
   };
+  const bool full = sp.mtv == RT && sp.ntv == CT;
   const int nchunk = (K + Q::KC - 1) / Q::KC;
   const int lr = lane & 15, lk = (lane >> 4) * 8;
   fetch(0);
@@ -509,30 +510,53 @@ AFQ_DEV PipeSplit pipe_gemm_mx(int K, int nr, int nc, GA ga, GB gb, unsigned sho
     const unsigned short* S = smem + (size_t)(ch & 1) * Q::STAGE;
     if (ch + 1 < nchunk) fetch((ch + 1) * Q::KC);
     bf8_t a[RT][P], b[CT][P];
+    if (full) {
+      // the wave holds RT x CT tiles: no per-MFMA conditions
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+      for (int i = 0; i < RT; ++i)
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-        if (i < sp.mtv)
+        for (int p = 0; p < P; ++p)
           a[i][p] = *(const bf8_t*)(S + ((size_t)p * (Q::ROWS + Q::COLS) + (sp.rt0 + i) * 16 + lr) *
                                             Q::PITCH + lk);
 #pragma unroll
-    for (int j = 0; j < CT; ++j)
+      for (int j = 0; j < CT; ++j)
 #pragma unroll
-      for (int p = 0; p < P; ++p)
-        if (j < sp.ntv)
+        for (int p = 0; p < P; ++p)
           b[j][p] = *(const bf8_t*)(S + ((size_t)p * (Q::ROWS + Q::COLS) + Q::ROWS +
                                          (sp.ct0 + j) * 16 + lr) * Q::PITCH + lk);
 #pragma unroll
-    for (int q = 0; q < SplitProds<P>::N; ++q)
+      for (int q = 0; q < SplitProds<P>::N; ++q)
 #pragma unroll
-      for (int i = 0; i < RT; ++i) {
-        if (i >= sp.mtv) continue;
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < CT; ++j)
-          if (j < sp.ntv)
+          for (int j = 0; j < CT; ++j)
             acc[i][j] = mfma_bf16(a[i][SplitProds<P>::a[q]], b[j][SplitProds<P>::b[q]], acc[i][j]);
-      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          if (i < sp.mtv)
+            a[i][p] = *(const bf8_t*)(S + ((size_t)p * (Q::ROWS + Q::COLS) + (sp.rt0 + i) * 16 + lr) *
+                                              Q::PITCH + lk);
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          if (j < sp.ntv)
+            b[j][p] = *(const bf8_t*)(S + ((size_t)p * (Q::ROWS + Q::COLS) + Q::ROWS +
+                                           (sp.ct0 + j) * 16 + lr) * Q::PITCH + lk);
+#pragma unroll
+      for (int q = 0; q < SplitProds<P>::N; ++q)
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          if (i >= sp.mtv) continue;
+#pragma unroll
+          for (int j = 0; j < CT; ++j)
+            if (j < sp.ntv)
+              acc[i][j] = mfma_bf16(a[i][SplitProds<P>::a[q]], b[j][SplitProds<P>::b[q]], acc[i][j]);
+        }
+    }
     if (ch + 1 < nchunk) store(smem + (size_t)((ch + 1) & 1) * Q::STAGE);
     __syncthreads();
   }
