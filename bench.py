@@ -401,6 +401,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "mixed", "mixed_fast", "mixed_energy"])
+    ap.add_argument("--energy-every", type=int, default=1,
+                    help="measure the local energy every this many steps (default 1)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="with --precision fp64: skip the mixed-precision runs beside it")
     ap.add_argument("--cpu-procs", type=int, default=None,
@@ -462,12 +464,13 @@ def main():
     ctx.init_walkers(sid, cfg.W)
     step0 = 0
 
-    def run_mode(name):
+    def run_mode(name, energy_every=None):
         """Warm-up then timed steps in one precision mode (HIP-event phases)."""
         nonlocal step0
         prec = PRECISIONS[name](afq)
         kw = dict(tau=cfg.tau, exp_method=afq.EXP_KRYLOV, exp_order=cfg.k,
-                  reorth_every=cfg.reorth_every, seed=0, precision=prec)
+                  reorth_every=cfg.reorth_every, seed=0, precision=prec,
+                  energy_every=energy_every or args.energy_every)
         energies = torch.zeros((1, args.steps, 2), dtype=torch.float64, device="cuda")
         log(f"{name}: warm-up {args.warmup} steps")
         ctx.propagate_batch(sid, n_steps=args.warmup, step0=step0, **kw)
@@ -490,7 +493,7 @@ def main():
         est = energies.cpu().numpy()[0]
         ex_ms, ex_n = prof["exchange"]
         ex_flops = exchange_flops_per_walker(cfg.M, cfg.N, cfg.G) * cfg.W
-        ex_avg_s = ex_ms / max(1, ex_n) / 1e3
+        ex_avg_s = ex_ms / max(1, ex_n) / 1e3 if ex_n else float("nan")
         if name == "fp64":
             # FP64 matrix cores: the algorithmic flops against the FP64 peak
             achieved, peak, kernel, fl = ex_flops / ex_avg_s, PEAK_FP64, "k_exchange", ex_flops
@@ -513,6 +516,7 @@ def main():
     main_run = run_mode(args.precision)
     cnt = ctx.get_counters(sid)
     others = {}
+    sparse = {}
     if args.precision == "fp64" and not args.no_mixed:
         for name in ("mixed_energy", "mixed"):
             r = run_mode(name)
@@ -521,6 +525,15 @@ def main():
                             "roofline": r["roofline"],
                             "phases_ms_per_step": {k: v["ms_per_step"]
                                                    for k, v in r["phases"].items()}}
+        if args.energy_every <= 1 and args.steps >= 10:
+            # the local energy measured every 10th step (the other steps form
+            # only the Coulomb vector for the force bias), FP64 and MIXED_ENERGY
+            for name in ("fp64", "mixed_energy"):
+                r = run_mode(name, energy_every=10)
+                sparse[name] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                "speedup_vs_fp64_every_step": r["value"] / main_run["value"],
+                                "phases_ms_per_step": {k: v["ms_per_step"]
+                                                       for k, v in r["phases"].items()}}
     ms_per_step = main_run["ms_per_step"]
     step_fl = step_flops_per_walker(cfg.M, cfg.N, cfg.G, cfg.k, cfg.reorth_every) * cfg.W
     out = {
@@ -540,7 +553,8 @@ def main():
                                f"Krylov k={cfg.k} QR every {cfg.reorth_every} tau={cfg.tau}",
                    "M": cfg.M, "N": cfg.N, "n_chol": cfg.G, "walkers": cfg.W, "k": cfg.k,
                    "tau": cfg.tau, "reorth_every": cfg.reorth_every,
-                   "precision": args.precision, "parallelism": "1 GPU"},
+                   "precision": args.precision, "energy_every": args.energy_every,
+                   "parallelism": "1 GPU"},
         "step_tflops": step_fl / (ms_per_step / 1e3) / 1e12,
         "step_frac_fp64_peak": step_fl / (ms_per_step / 1e3) / PEAK_FP64,
         "roofline": main_run["roofline"],
@@ -548,6 +562,7 @@ def main():
         "counters": cnt,
         "energy_last_step": main_run["energy_last_step"],
         "mixed": others,
+        "energy_every_10": sparse,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -100,7 +100,10 @@ typedef struct {
   int32_t reorth_every;  /* QR after global step t when (t+1) % reorth_every == 0 */
   int32_t precision;     /* AFQ_PREC_FP64, AFQ_PREC_MIXED or AFQ_PREC_MIXED_FAST   */
   int32_t n_steps;       /* steps to run                                         */
-  int32_t energy_every;  /* 1 = local energy every step (0 is read as 1)         */
+  int32_t energy_every;  /* local energy every this many steps (and at the last);
+                            0 is read as 1.  Other steps form only the Coulomb
+                            vector the next force bias needs, a ~100x cheaper
+                            product than the local-energy contraction          */
   double e0;             /* energy shift E0; NaN = trial energy (fixed)          */
   uint64_t seed;         /* Philox key word 0 (word 1 is the system id)          */
   uint64_t step0;        /* global index of the first step (RNG counter, QR)     */
@@ -199,7 +202,8 @@ afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4);
  * and launch counts of the first n phases (AFQ_PH_*) and clears them. */
 enum {
   AFQ_PH_FIELDS = 0, AFQ_PH_FORCE_BIAS, AFQ_PH_OPBUILD, AFQ_PH_ONEBODY, AFQ_PH_EXPONENTIAL,
-  AFQ_PH_OVERLAP, AFQ_PH_WEIGHT, AFQ_PH_QR, AFQ_PH_EXCHANGE, AFQ_PH_ENERGY, AFQ_PH_COUNT
+  AFQ_PH_OVERLAP, AFQ_PH_WEIGHT, AFQ_PH_QR, AFQ_PH_EXCHANGE, AFQ_PH_ENERGY, AFQ_PH_COULOMB,
+  AFQ_PH_COUNT
 };
 afq_status afq_profile(afq_ctx* ctx, int enable);
 afq_status afq_profile_read(afq_ctx* ctx, double* ms_out, int64_t* launches_out, int n);

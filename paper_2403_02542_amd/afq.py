@@ -30,7 +30,7 @@ EXPORTED = (
     "afq_profile_read", "afq_sync", "afq_autotune",
 )
 PHASES = ("fields", "force_bias", "opbuild", "onebody", "exponential", "overlap", "weight", "qr",
-          "exchange", "energy")
+          "exchange", "energy", "coulomb")
 
 
 class AfqError(RuntimeError):

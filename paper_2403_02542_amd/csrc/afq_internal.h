@@ -72,6 +72,8 @@ struct SysDev {
   int x_ga = 0, x_wb = 0;
   // tuned column blocks of the operator-orbital product (0 = default)
   int mv_ct = 0;
+  // partial sums of the Coulomb-vector-only product (allocated on first use)
+  double* coul_ws = nullptr;
   // adjoint workspace (allocated on first use, sized for the walker count)
   double* adj_ws = nullptr;
   size_t adj_ws_n = 0;        // doubles
@@ -175,6 +177,12 @@ int matvec_max_blocks(int M);
 // One operator-orbital product out = A in over all walkers (tuner probe).
 hipError_t launch_matvec_probe(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                                double* out_im, hipStream_t st);
+// Coulomb vector alone (ell of every walker and Cholesky block, no exchange
+// term), for the steps that do not measure the energy.  part: scratch of
+// coulomb_slices(W, G, N M) x W x G doubles.
+int coulomb_slices(int W, int G, int NM);
+hipError_t launch_coulomb(SysDev& s, const double* th_re, const double* th_im, double* part,
+                          hipStream_t st);
 // Admissible (GA, WB) tile shapes for N, best first by the occupancy model.
 void exchange_candidates(int N, std::vector<int2>& out);
 hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* ell_im,

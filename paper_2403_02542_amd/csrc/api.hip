@@ -410,9 +410,15 @@ afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_para
   const double* x = P.fields ? P.fields + (size_t)si * s.W * s.G : nullptr;
   TRY(step_front(ctx, sid, s, P, x, t, nullptr, 0, ctx->stream));
   const int every = P.energy_every > 0 ? P.energy_every : 1;
-  TRY(step_exchange(ctx, s, P, ctx->stream));
-  if ((si + 1) % every == 0 || si + 1 == P.n_steps)
+  const bool measure = (si + 1) % every == 0 || si + 1 == P.n_steps;
+  if (measure) {
+    TRY(step_exchange(ctx, s, P, ctx->stream));
     TRY(step_energy(ctx, s, P, si, row, nullptr, 0, ctx->stream));
+  } else {
+    // no energy this step: the next force bias needs only ell
+    Phase ph(ctx, AFQ_PH_COULOMB);
+    HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, ctx->stream));
+  }
   return AFQ_OK;
 }
 
@@ -880,6 +886,7 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   s.thb = nullptr;
   s.adj_ws = nullptr;
   s.adj_ws_n = 0;
+  s.coul_ws = nullptr;
   if (s.mx_pieces) s.mx_pieces = -1;  // pieces of L stay; Theta buffer re-made
   auto& own = s.walker_allocs;
   s.W = (int)n_walkers;
@@ -984,6 +991,11 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     if (energy_pieces(P->precision))
       TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], energy_pieces(P->precision)));
     ss[i]->op_pieces = op_pieces_of(P->precision);
+    if (P->energy_every > 1 && !ss[i]->coul_ws) {
+      SysDev& s = *ss[i];
+      const size_t n = (size_t)coulomb_slices(s.W, s.G, s.N * s.M) * s.W * s.G;
+      TRY(dalloc(ctx, s.walker_allocs, &s.coul_ws, n));
+    }
     HIPCHK(hipMemsetAsync(ss[i]->counters, 0, 4 * sizeof(int), ctx->stream));
   }
   if (mode == AFQ_SCHED_SERIAL) {

@@ -411,3 +411,56 @@ void exchange_candidates(int N, std::vector<int2>& out) {
   std::sort(cs.begin(), cs.end(), [](const C& a, const C& b) { return a.eff > b.eff; });
   for (const C& c : cs) out.push_back(int2{c.ga, c.wb});
 }
+
+// ------------------------------------------------------------ Coulomb vector only
+// ell_g^w = 2 tr T_g^w = 2 sum_(i,p) (Psi_T^T L_g)[i][p] Theta^w[p][i]: one
+// product [W x NM] x [NM x G] per plane, for the steps that do not measure the
+// energy (the force bias needs ell every step; the exchange term only when the
+// energy is measured).  K = NM is cut into S slices (batch entries writing
+// partial sums), summed in slice order into ell.
+
+namespace {
+
+__global__ void k_sum_slices(const double* __restrict__ part, int S, int W, int G, int G1,
+                             double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)W * G;
+  if (e >= n) return;
+  double v = 0.0;
+  for (int q = 0; q < S; ++q) v += part[q * n + e];
+  const int64_t w = e / G, g = e - w * G;
+  out[w * G1 + g] = v;
+}
+
+}  // namespace
+
+int coulomb_slices(int W, int G, int NM) {
+  const int tiles = ((W + 127) / 128) * ((G + 127) / 128);
+  int S = 1;
+  while (S < 16 && tiles * S < 512 && NM % (2 * S) == 0 && NM / (2 * S) >= 256) S *= 2;
+  return S;
+}
+
+hipError_t launch_coulomb(SysDev& s, const double* th_re, const double* th_im, double* part,
+                          hipStream_t st) {
+  const int W = s.W, G = s.G, G1 = G + 1;
+  const int NM = s.N * s.M;
+  const int S = coulomb_slices(W, G, NM);
+  const int kc = NM / S;
+  const double* planes[2] = {th_re, th_im};
+  double* outs[2] = {s.ell_re, s.ell_im};
+  for (int pl = 0; pl < 2; ++pl) {
+    GemmArgs c{};
+    c.A = planes[pl]; c.sAb = kc; c.sAr = NM; c.sAk = 1; c.sAkb = 0;
+    c.B = s.Lx; c.sBb = kc; c.sBc = NM; c.sBk = 1; c.sBkb = 0;
+    c.C = part; c.sCb = (int64_t)W * G; c.sCr = G; c.sCc = 1;
+    c.R = W; c.Cn = G; c.K = kc; c.kin = kc; c.batch = S; c.alpha = 2.0; c.beta = 0.0;
+    hipError_t e = launch_gemm(c, st);
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)W * G;
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, S,
+                       W, G, G1, outs[pl]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
