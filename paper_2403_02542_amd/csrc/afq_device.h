@@ -295,7 +295,10 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
   };
   const int nchunk = (K + BK - 1) / BK;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool full = sp.mtv == RT && sp.ntv == CT;
+  // tiles beyond the valid ones hold zeros in the stage, so a wave with any
+  // valid tile runs the condition-free loop over all RT x CT (the extra
+  // products are discarded by the caller's bounds)
+  const bool full = sp.mtv > 0 && sp.ntv > 0;
   fetch(0);
   store(smem);
   __syncthreads();
@@ -304,7 +307,7 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
     const double* Bs = As + P::ROWS * LDK;
     if (ch + 1 < nchunk) fetch((ch + 1) * BK);
     if (full) {
-      // the wave holds RT x CT tiles: no per-MFMA conditions
+      // no per-MFMA conditions
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         double a[RT], b[CT];
