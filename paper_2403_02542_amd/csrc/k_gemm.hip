@@ -206,11 +206,15 @@ __global__ __launch_bounds__(OpTile<PC>::NT) void k_opbuild(int W, int G, int64_
 // Eight waves: two rows of waves split the 2N rows (RT = ceil(TR / 2) row
 // tiles each) and four columns of waves hold up to two column tiles each;
 // K runs in chunks of 32 so that each fetch from HBM covers 8 MFMA k-steps.
-// (The BF16-split engine keeps the single row of four waves: its fragment
-// registers do not leave room for the split rows.)
-template <int PC>
+// Seven row tiles (N = 49..56) would leave one of the eight tiles of two
+// wave rows empty, so there one row of eight waves holds all seven row tiles
+// and one column tile each.  (The BF16-split engine keeps the single row of
+// four waves: its fragment registers do not leave room for the split rows.)
+template <int PC, int RT>
 struct MvCfg {
-  static constexpr int WR = PC == 0 ? 2 : 1, WC = 4, CT = 2, BK = 32;
+  static constexpr bool ONE_ROW = PC == 0 && RT == 7;
+  static constexpr int WR = PC == 0 && !ONE_ROW ? 2 : 1, WC = ONE_ROW ? 8 : 4;
+  static constexpr int CT = ONE_ROW ? 1 : 2, BK = 32;
   static constexpr int NT = 64 * WR * WC;
 };
 
@@ -226,7 +230,7 @@ struct VecOut {
 };
 
 template <int RT, int PC>
-__global__ __launch_bounds__(MvCfg<PC>::NT) void k_matvec(int W, int N, int M, VecRef v,
+__global__ __launch_bounds__((MvCfg<PC, RT>::NT)) void k_matvec(int W, int N, int M, VecRef v,
                                                        const double* __restrict__ A_re,
                                                        const double* __restrict__ A_im, VecOut o,
                                                        int mode, double inv_n, VecOut sum,
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(MvCfg<PC>::NT) void k_matvec(int W, int N, int M, V
     const int64_t p = c0 + c;
     return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
   };
-  using C = MvCfg<PC>;
+  using C = MvCfg<PC, RT>;
   pipe_run<C::WR, C::WC, RT, C::CT, PC, false, false, C::BK>(
       2 * M, nr, nc, ga, gb, smem, [&](int r, int c, double val) {
         if (r < nr && c < nc) {
@@ -278,15 +282,17 @@ __global__ __launch_bounds__(MvCfg<PC>::NT) void k_matvec(int W, int N, int M, V
 
 int matvec_col_blocks(int M) {
   const int TC = (M + 15) / 16;
-  const int per = MvCfg<0>::WC * MvCfg<0>::CT;   // same for both engines
+  const int per = MvCfg<0, 4>::WC * MvCfg<0, 4>::CT;   // the same for every shape
   return (TC + per - 1) / per;
 }
-static_assert(MvCfg<0>::WC * MvCfg<0>::CT == MvCfg<3>::WC * MvCfg<3>::CT, "column blocks");
+static_assert(MvCfg<0, 4>::WC * MvCfg<0, 4>::CT == MvCfg<3, 4>::WC * MvCfg<3, 4>::CT &&
+                  MvCfg<0, 4>::WC * MvCfg<0, 4>::CT == MvCfg<0, 7>::WC * MvCfg<0, 7>::CT,
+              "column blocks");
 
 template <int RT, int PC>
 hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                      hipStream_t st) {
-  using C = MvCfg<PC>;
+  using C = MvCfg<PC, RT>;
   constexpr size_t lds = pipe_lds_bytes<C::WR, C::WC, RT, C::CT, PC, C::BK>();
   static bool lds_ok = false;
   if (!lds_ok) {
@@ -305,15 +311,15 @@ template <int PC>
 hipError_t run_matvec_p(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                         hipStream_t st) {
   const int TR = (2 * s.N + 15) / 16;
-  const int rpw = (TR + MvCfg<PC>::WR - 1) / MvCfg<PC>::WR;
-  if constexpr (MvCfg<PC>::WR == 2) {
-    if (rpw <= 3) return matvec_rt<3, PC>(s, v, o, mode, inv_n, sum, st);
-    if (rpw <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
-    if (rpw <= 5) return matvec_rt<5, PC>(s, v, o, mode, inv_n, sum, st);
+  if constexpr (PC == 0) {
+    if (TR <= 6) return matvec_rt<3, PC>(s, v, o, mode, inv_n, sum, st);
+    if (TR == 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
+    if (TR <= 8) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
+    if (TR <= 10) return matvec_rt<5, PC>(s, v, o, mode, inv_n, sum, st);
   } else {
-    if (rpw <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
-    if (rpw <= 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
-    if (rpw <= 10) return matvec_rt<10, PC>(s, v, o, mode, inv_n, sum, st);
+    if (TR <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
+    if (TR <= 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
+    if (TR <= 10) return matvec_rt<10, PC>(s, v, o, mode, inv_n, sum, st);
   }
   return hipErrorInvalidValue;
 }
