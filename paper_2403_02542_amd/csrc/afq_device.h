@@ -51,6 +51,29 @@ AFQ_DEV double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+// Wave sum on the VALU's data-parallel lane moves (no LDS): pairs, quads,
+// half rows and rows of 16 lanes by quad permutations and mirrors, then rows
+// 0+1 and 2+3 by the broadcast of lane 15 into the next row, and the total
+// by the broadcast of lane 31 into rows 2 and 3; lane 63 holds it and every
+// lane gets it back.  The order of the additions is fixed.
+template <int CTRL, int ROWS>
+AFQ_DEV double dpp_move(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, false);
+  return __hiloint2double(h2, l2);
+}
+AFQ_DEV double wave_sum_dpp(double v) {
+  v += dpp_move<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_move<0x140, 0xf>(v);   // row_mirror
+  v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
 AFQ_DEV double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
