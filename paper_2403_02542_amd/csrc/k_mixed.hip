@@ -58,6 +58,7 @@ constexpr int M_SUPER_G = 4, M_SUPER_W = 8;
 // Up to 13 column tiles (208 columns): two walkers per tile up to N = 52, so
 // every row fragment loaded from HBM feeds both walkers' products.
 constexpr int M_CTMAX = 13;
+constexpr int M_JG = 4;                    // column tiles per MFMA group
 inline int mx_ct(int TC) { return TC <= 4 ? 4 : TC <= 7 ? 7 : TC <= 10 ? 10 : 13; }
 
 template <int P>
@@ -184,20 +185,29 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
       fetch_b((ch + 1) * M_KC);
     }
     if (full) {
-      // all row tiles present: no per-MFMA conditions
+      // all row tiles present: no per-MFMA conditions.  Column tiles go in
+      // groups of M_JG with the piece product outermost, so consecutive
+      // MFMAs feed M_RT * M_JG different accumulators.
 #pragma unroll
-      for (int j = 0; j < CT; ++j) {
-        bf8_t b[P];
+      for (int j0 = 0; j0 < CT; j0 += M_JG) {
+        bf8_t b[M_JG][P];
 #pragma unroll
-        for (int p = 0; p < P; ++p)
-          b[p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + j * 16 + lr) * M_PITCH + lk);
+        for (int jj = 0; jj < M_JG; ++jj)
 #pragma unroll
-        for (int i = 0; i < M_RT; ++i)
+          for (int p = 0; p < P; ++p)
+            if (j0 + jj < CT)
+              b[jj][p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + (j0 + jj) * 16 + lr) * M_PITCH + lk);
 #pragma unroll
-          for (int q = 0; q < MxProds<P>::N; ++q) {
-            const uint4 av = afr[i][MxProds<P>::a[q]];
-            acc[i][j] = mfma_bf16(*(const bf8_t*)&av, b[MxProds<P>::b[q]], acc[i][j]);
-          }
+        for (int q = 0; q < MxProds<P>::N; ++q)
+#pragma unroll
+          for (int jj = 0; jj < M_JG; ++jj)
+#pragma unroll
+            for (int i = 0; i < M_RT; ++i)
+              if (j0 + jj < CT) {
+                const uint4 av = afr[i][MxProds<P>::a[q]];
+                acc[i][j0 + jj] =
+                    mfma_bf16(*(const bf8_t*)&av, b[jj][MxProds<P>::b[q]], acc[i][j0 + jj]);
+              }
       }
     } else {
 #pragma unroll
