@@ -203,16 +203,18 @@ __global__ __launch_bounds__(OpTile<PC>::NT) void k_opbuild(int W, int G, int64_
 //   col p:       [ A_re[p][q],   A_im[p][q] ]
 // mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
 
-// Eight waves: two rows of waves split the 2N rows (RT = ceil(TR / 2) row
-// tiles each) and four columns of waves hold up to two column tiles each;
-// K runs in chunks of 32 so that each fetch from HBM covers 8 MFMA k-steps.
-// Seven row tiles (N = 49..56) would leave one of the eight tiles of two
-// wave rows empty, so there one row of eight waves holds all seven row tiles
-// and one column tile each.  (The BF16-split engine keeps the single row of
-// four waves: its fragment registers do not leave room for the split rows.)
+// FP64 engine: eight waves, two rows of waves split the 2N rows (RT =
+// ceil(TR / 2) row tiles each) and four columns of waves hold up to two
+// column tiles each; K runs in chunks of 32 so that each fetch from HBM
+// covers 8 MFMA k-steps.  Seven row tiles (N = 49..56) would leave one of the
+// eight tiles of two wave rows empty, so there one row of eight waves holds
+// all seven row tiles and one column tile each.  The BF16-split engine keeps
+// a single row of waves (its fragment registers leave no room for split
+// rows): eight waves of one column tile up to seven row tiles, so that two
+// waves share each SIMD, and four waves of two column tiles for ten.
 template <int PC, int RT>
 struct MvCfg {
-  static constexpr bool ONE_ROW = PC == 0 && RT == 7;
+  static constexpr bool ONE_ROW = PC == 0 ? RT == 7 : RT <= 7;
   static constexpr int WR = PC == 0 && !ONE_ROW ? 2 : 1, WC = ONE_ROW ? 8 : 4;
   static constexpr int CT = ONE_ROW ? 1 : 2, BK = 32;
   static constexpr int NT = 64 * WR * WC;
