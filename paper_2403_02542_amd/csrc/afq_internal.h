@@ -68,6 +68,12 @@ struct SysDev {
   // BF16 pieces of the operator build, the one-body half-steps and the
   // operator-orbital products of the current propagate call (0 = FP64)
   int op_pieces = 0;
+  // pieces of the operator, split once per step for the BF16-split
+  // operator-orbital products: [P][W M][Kq], K = (re q | im q), Kq = 2M
+  // padded to a multiple of 32 (allocated for three pieces on first use)
+  unsigned short* Ab = nullptr;
+  int64_t Ab_ps = 0;
+  int Kq = 0;
   // tuned tile shape of the local-energy contraction (0 = occupancy model)
   int x_ga = 0, x_wb = 0;
   // tuned column blocks of the operator-orbital product (0 = default)
@@ -129,7 +135,25 @@ hipError_t launch_lbar(const SysDev& s, hipStream_t st);
 hipError_t launch_axpy_L(const SysDev& s, const double* coef, double alpha, double* out,
                          hipStream_t st);
 hipError_t launch_force_bias(SysDev& s, const double* x, double tau, hipStream_t st);
+// Orbital-set views for the operator-orbital product: element (w, j, p) at
+// w * sw + j * sj + p of the re / im planes.
+struct VecRef {
+  const double* re;
+  const double* im;
+  int64_t sw, sj;
+};
+struct VecOut {
+  double* re;
+  double* im;
+  int64_t sw, sj;
+};
 hipError_t launch_opbuild(SysDev& s, hipStream_t st);
+// BF16-split operator-orbital product out = A v (mode 0) or out = A v / n,
+// sum += out (mode 1, a Taylor term), with the operator pieces in s.Ab.
+hipError_t launch_matvec_mx(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+                            hipStream_t st);
+// Split the operator planes A_re / A_im into s.op_pieces pieces in s.Ab.
+hipError_t launch_split_op(SysDev& s, hipStream_t st);
 hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                           double* out_im, hipStream_t st);
 // Krylov exponential of the operator on every orbital: out = krylov_k(A, in);

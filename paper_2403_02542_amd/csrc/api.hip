@@ -887,6 +887,7 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   s.adj_ws = nullptr;
   s.adj_ws_n = 0;
   s.coul_ws = nullptr;
+  s.Ab = nullptr;
   if (s.mx_pieces) s.mx_pieces = -1;  // pieces of L stay; Theta buffer re-made
   auto& own = s.walker_allocs;
   s.W = (int)n_walkers;
@@ -991,6 +992,12 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     if (energy_pieces(P->precision))
       TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], energy_pieces(P->precision)));
     ss[i]->op_pieces = op_pieces_of(P->precision);
+    if (ss[i]->op_pieces > 0 && !ss[i]->Ab) {
+      SysDev& s = *ss[i];
+      s.Kq = (2 * s.M + 31) / 32 * 32;
+      s.Ab_ps = (int64_t)s.W * s.M * s.Kq;
+      TRY(dalloc(ctx, s.walker_allocs, &s.Ab, (size_t)3 * s.Ab_ps));
+    }
     if (P->energy_every > 1 && !ss[i]->coul_ws) {
       SysDev& s = *ss[i];
       const size_t n = (size_t)coulomb_slices(s.W, s.G, s.N * s.M) * s.W * s.G;

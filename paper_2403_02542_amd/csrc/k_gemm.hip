@@ -203,40 +203,26 @@ __global__ __launch_bounds__(OpTile<PC>::NT) void k_opbuild(int W, int G, int64_
 //   col p:       [ A_re[p][q],   A_im[p][q] ]
 // mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
 
-// FP64 engine: eight waves, two rows of waves split the 2N rows (RT =
-// ceil(TR / 2) row tiles each) and four columns of waves hold up to two
-// column tiles each; K runs in chunks of 32 so that each fetch from HBM
-// covers 8 MFMA k-steps.  Seven row tiles (N = 49..56) would leave one of the
-// eight tiles of two wave rows empty, so there one row of eight waves holds
-// all seven row tiles and one column tile each.  The BF16-split engine keeps
-// a single row of waves (its fragment registers leave no room for split
-// rows): eight waves of one column tile up to seven row tiles, so that two
-// waves share each SIMD, and four waves of two column tiles for ten.
-template <int PC, int RT>
+// Eight waves: two rows of waves split the 2N rows (RT = ceil(TR / 2) row
+// tiles each) and four columns of waves hold up to two column tiles each;
+// K runs in chunks of 32 so that each fetch from HBM covers 8 MFMA k-steps.
+// Seven row tiles (N = 49..56) would leave one of the eight tiles of two
+// wave rows empty, so there one row of eight waves holds all seven row tiles
+// and one column tile each.  (The BF16-split product is k_matvec_mx.)
+template <int RT>
 struct MvCfg {
-  static constexpr bool ONE_ROW = PC == 0 ? RT == 7 : RT <= 7;
-  static constexpr int WR = PC == 0 && !ONE_ROW ? 2 : 1, WC = ONE_ROW ? 8 : 4;
+  static constexpr bool ONE_ROW = RT == 7;
+  static constexpr int WR = ONE_ROW ? 1 : 2, WC = ONE_ROW ? 8 : 4;
   static constexpr int CT = ONE_ROW ? 1 : 2, BK = 32;
   static constexpr int NT = 64 * WR * WC;
 };
 
-struct VecRef {
-  const double* re;
-  const double* im;
-  int64_t sw, sj;  // walker / orbital strides (elements)
-};
-struct VecOut {
-  double* re;
-  double* im;
-  int64_t sw, sj;
-};
-
-template <int RT, int PC>
-__global__ __launch_bounds__((MvCfg<PC, RT>::NT)) void k_matvec(int W, int N, int M, VecRef v,
-                                                       const double* __restrict__ A_re,
-                                                       const double* __restrict__ A_im, VecOut o,
-                                                       int mode, double inv_n, VecOut sum,
-                                                       int n_ct) {
+template <int RT>
+__global__ __launch_bounds__((MvCfg<RT>::NT)) void k_matvec(int W, int N, int M, VecRef v,
+                                                         const double* __restrict__ A_re,
+                                                         const double* __restrict__ A_im, VecOut o,
+                                                         int mode, double inv_n, VecOut sum,
+                                                         int n_ct) {
   extern __shared__ double smem[];
   int w, ct;
   if (!xcd_swizzle(blockIdx.x, n_ct, W, w, ct)) return;
@@ -263,8 +249,8 @@ __global__ __launch_bounds__((MvCfg<PC, RT>::NT)) void k_matvec(int W, int N, in
     const int64_t p = c0 + c;
     return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
   };
-  using C = MvCfg<PC, RT>;
-  pipe_run<C::WR, C::WC, RT, C::CT, PC, false, false, C::BK>(
+  using C = MvCfg<RT>;
+  pipe_run<C::WR, C::WC, RT, C::CT, 0, false, false, C::BK>(
       2 * M, nr, nc, ga, gb, smem, [&](int r, int c, double val) {
         if (r < nr && c < nc) {
           const bool im_row = r >= N;
@@ -284,54 +270,40 @@ __global__ __launch_bounds__((MvCfg<PC, RT>::NT)) void k_matvec(int W, int N, in
 
 int matvec_col_blocks(int M) {
   const int TC = (M + 15) / 16;
-  const int per = MvCfg<0, 4>::WC * MvCfg<0, 4>::CT;   // the same for every shape
+  const int per = MvCfg<4>::WC * MvCfg<4>::CT;   // the same for every shape
   return (TC + per - 1) / per;
 }
-static_assert(MvCfg<0, 4>::WC * MvCfg<0, 4>::CT == MvCfg<3, 4>::WC * MvCfg<3, 4>::CT &&
-                  MvCfg<0, 4>::WC * MvCfg<0, 4>::CT == MvCfg<0, 7>::WC * MvCfg<0, 7>::CT,
-              "column blocks");
+static_assert(MvCfg<4>::WC * MvCfg<4>::CT == MvCfg<7>::WC * MvCfg<7>::CT, "column blocks");
 
-template <int RT, int PC>
+template <int RT>
 hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                      hipStream_t st) {
-  using C = MvCfg<PC, RT>;
-  constexpr size_t lds = pipe_lds_bytes<C::WR, C::WC, RT, C::CT, PC, C::BK>();
+  using C = MvCfg<RT>;
+  constexpr size_t lds = pipe_lds_bytes<C::WR, C::WC, RT, C::CT, 0, C::BK>();
   static bool lds_ok = false;
   if (!lds_ok) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT, PC>,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     lds_ok = true;
   }
-  const int n_ct = s.mv_ct > 0 ? s.mv_ct : matvec_col_blocks(s.M);
-  hipLaunchKernelGGL((k_matvec<RT, PC>), dim3(xcd_grid(s.W, n_ct)), dim3(C::NT), lds,
-                     st, s.W, s.N, s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
+  // a tuned count below the minimum would leave column tiles out
+  const int n_ct = max(s.mv_ct, matvec_col_blocks(s.M));
+  hipLaunchKernelGGL((k_matvec<RT>), dim3(xcd_grid(s.W, n_ct)), dim3(C::NT), lds, st, s.W, s.N,
+                     s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
   return hipGetLastError();
-}
-
-template <int PC>
-hipError_t run_matvec_p(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
-                        hipStream_t st) {
-  const int TR = (2 * s.N + 15) / 16;
-  if constexpr (PC == 0) {
-    if (TR <= 6) return matvec_rt<3, PC>(s, v, o, mode, inv_n, sum, st);
-    if (TR == 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
-    if (TR <= 8) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
-    if (TR <= 10) return matvec_rt<5, PC>(s, v, o, mode, inv_n, sum, st);
-  } else {
-    if (TR <= 4) return matvec_rt<4, PC>(s, v, o, mode, inv_n, sum, st);
-    if (TR <= 7) return matvec_rt<7, PC>(s, v, o, mode, inv_n, sum, st);
-    if (TR <= 10) return matvec_rt<10, PC>(s, v, o, mode, inv_n, sum, st);
-  }
-  return hipErrorInvalidValue;
 }
 
 // The operator-orbital product in the system's current precision.
 hipError_t run_matvec(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                       hipStream_t st) {
-  if (s.op_pieces == 3) return run_matvec_p<3>(s, v, o, mode, inv_n, sum, st);
-  if (s.op_pieces == 2) return run_matvec_p<2>(s, v, o, mode, inv_n, sum, st);
-  return run_matvec_p<0>(s, v, o, mode, inv_n, sum, st);
+  if (s.op_pieces > 0) return launch_matvec_mx(s, v, o, mode, inv_n, sum, st);
+  const int TR = (2 * s.N + 15) / 16;
+  if (TR <= 6) return matvec_rt<3>(s, v, o, mode, inv_n, sum, st);
+  if (TR == 7) return matvec_rt<7>(s, v, o, mode, inv_n, sum, st);
+  if (TR <= 8) return matvec_rt<4>(s, v, o, mode, inv_n, sum, st);
+  if (TR <= 10) return matvec_rt<5>(s, v, o, mode, inv_n, sum, st);
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------ Krylov pieces
@@ -647,9 +619,10 @@ hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, d
 }
 
 hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
-  if (s.op_pieces == 3) return opbuild_p<3>(s, st);
-  if (s.op_pieces == 2) return opbuild_p<2>(s, st);
-  return opbuild_p<0>(s, st);
+  if (s.op_pieces == 0) return opbuild_p<0>(s, st);
+  const hipError_t e = s.op_pieces == 3 ? opbuild_p<3>(s, st) : opbuild_p<2>(s, st);
+  if (e != hipSuccess) return e;
+  return launch_split_op(s, st);   // pieces for the operator-orbital products
 }
 
 hipError_t launch_taylor(SysDev& s, int k, const double* in_re, const double* in_im,

@@ -7,6 +7,9 @@
 //  * k_exchange_mx: the local-energy contraction of k_exchange.hip with the
 //    T_g blocks formed from BF16-split (Psi_T^T L_g) and Theta; the N x N
 //    blocks are reduced in float64 exactly as in the FP64 kernel.
+//  * k_split_op / k_matvec_mx: the operator-orbital product A^w psi of the
+//    exponential with the operator split once per step and the orbitals
+//    split while they are staged.
 #include "afq_device.h"
 #include "afq_internal.h"
 
@@ -371,6 +374,229 @@ hipError_t launch_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- operator pieces
+// Ab[p][w M + r][k] = piece p of A_re[w][r][k] (k < M), of A_im[w][r][k - M]
+// (M <= k < 2M), 0 up to Kq.
+__global__ void k_split_op(const double* __restrict__ are, const double* __restrict__ aim,
+                           int64_t R, int M, int Kq, int P, int64_t piece_stride,
+                           unsigned short* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R * Kq) return;
+  const int64_t r = e / Kq;
+  const int k = (int)(e - r * Kq);
+  double x = k < M ? are[r * M + k] : (k < 2 * M ? aim[r * M + (k - M)] : 0.0);
+  for (int p = 0; p < P; ++p) {
+    const unsigned short b = bf16_bits_rn((float)x);
+    out[p * piece_stride + e] = b;
+    x -= (double)bf16_bits_to_f(b);
+  }
+}
+
+// ---------------------------------------------------------------- A^w psi
+// For walker w: out[j][p] = sum_q A^w[p][q] v[j][q] (complex) as one real
+// product of K = 2M: rows p of [A_re | A_im] (the pre-split operator, loaded
+// by each wave straight into registers) times columns (plane, j) of the real
+// form of the orbitals, [v_re | -v_im] and [v_im | v_re], which are split
+// while they are staged in LDS.  One workgroup per walker and block of up to
+// 8 RT row tiles; all 2N columns in one tile (CT >= ceil(2N / 16)).
+constexpr int V_JG = 2;                    // column tiles per MFMA group
+
+template <int CT, int P, int RT>
+__global__ __launch_bounds__(MT_) void k_matvec_mx(int W, int N, int M, int Kq, int nrb,
+                                                   const unsigned short* __restrict__ Ab,
+                                                   int64_t Ab_ps, VecRef v, VecOut o, int mode,
+                                                   double inv_n, VecOut sum) {
+  extern __shared__ double smem[];
+  unsigned short* lds = (unsigned short*)smem;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int w = blockIdx.x / nrb, rb = blockIdx.x - w * nrb;
+  if (w >= W) return;
+  const int TR_all = (M + 15) >> 4;
+  const int tpb = (TR_all + nrb - 1) / nrb;
+  const int tr0 = rb * tpb;
+  const int TR = min(tpb, TR_all - tr0);
+  if (TR <= 0) return;
+  const int row0 = tr0 * 16;
+  const int nr = min(TR * 16, M - row0), nc = 2 * N;
+  const int rpw = (TR + MW - 1) / MW;
+  const int rt0 = wave * rpw;
+  const int mtv = max(0, min(rpw, TR - rt0));
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+
+  // ---- row operand: this lane's operator rows, straight from global memory
+  const unsigned short* Aw = Ab + ((int64_t)w * M + row0) * Kq;
+  bool arow_ok[RT];
+  const unsigned short* aptr[RT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    const int r = (rt0 + i) * 16 + lr;
+    arow_ok[i] = (i < mtv) && (r < nr);
+    aptr[i] = Aw + (int64_t)(arow_ok[i] ? r : 0) * Kq + lk;
+  }
+  uint4 afr[RT][P];
+  auto fetch_a = [&](int k0, uint4 (&dst)[RT][P]) {
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        dst[i][p] = arow_ok[i] ? *(const uint4*)(aptr[i] + p * Ab_ps + k0) : make_uint4(0, 0, 0, 0);
+  };
+
+  // ---- column operand: float64 orbitals, split into the LDS stage
+  // [stage][p][col][M_PITCH] in units of four k (eight units per column)
+  constexpr int BROWS = CT * 16;
+  constexpr int BSTAGE = P * BROWS * M_PITCH;
+  constexpr int UNITS = BROWS * (M_KC / 4);
+  constexpr int PFU = (UNITS + MT_ - 1) / MT_;
+  const double* vre = v.re + (int64_t)w * v.sw;
+  const double* vim = v.im + (int64_t)w * v.sw;
+  auto vget = [&](int c, int k) -> double {
+    const bool im_row = c >= N;
+    const int j = im_row ? c - N : c;
+    if (k < M) return im_row ? vim[j * v.sj + k] : vre[j * v.sj + k];
+    const int q = k - M;
+    if (q >= M) return 0.0;
+    return im_row ? vre[j * v.sj + q] : -vim[j * v.sj + q];
+  };
+  double pf[PFU][4];
+  auto fetch_b = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < PFU; ++i) {
+      const int u = tid + i * MT_;
+      const int c = u >> 3, k = k0 + (u & 7) * 4;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) pf[i][t] = (u < UNITS && c < nc) ? vget(c, k + t) : 0.0;
+    }
+  };
+  auto store_b = [&](unsigned short* S) {
+#pragma unroll
+    for (int i = 0; i < PFU; ++i) {
+      const int u = tid + i * MT_;
+      if (u < UNITS) {
+        const int c = u >> 3, k = (u & 7) * 4;
+        double x[4] = {pf[i][0], pf[i][1], pf[i][2], pf[i][3]};
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          unsigned short b[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            b[t] = bf16_bits_rn((float)x[t]);
+            x[t] -= (double)bf16_bits_to_f(b[t]);
+          }
+          uint2 q;
+          q.x = (unsigned)b[0] | ((unsigned)b[1] << 16);
+          q.y = (unsigned)b[2] | ((unsigned)b[3] << 16);
+          *(uint2*)(S + ((size_t)p * BROWS + c) * M_PITCH + k) = q;
+        }
+      }
+    }
+  };
+
+  f4_t acc[RT][CT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  // invalid row fragments and the columns beyond 2N hold zeros, so a wave
+  // with any valid row tile runs the loop without per-MFMA conditions
+  const bool active = mtv > 0;
+  const int nchunk = Kq / M_KC;
+  fetch_a(0, afr);
+  fetch_b(0);
+  store_b(lds);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const unsigned short* Bs = lds + (ch & 1) * BSTAGE;
+    uint4 anx[RT][P];
+    const bool more = ch + 1 < nchunk;
+    if (more) {
+      fetch_a((ch + 1) * M_KC, anx);
+      fetch_b((ch + 1) * M_KC);
+    }
+    if (active) {
+#pragma unroll
+      for (int j0 = 0; j0 < CT; j0 += V_JG) {
+        bf8_t b[V_JG][P];
+#pragma unroll
+        for (int jj = 0; jj < V_JG; ++jj)
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            if (j0 + jj < CT)
+              b[jj][p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + (j0 + jj) * 16 + lr) * M_PITCH + lk);
+#pragma unroll
+        for (int q = 0; q < MxProds<P>::N; ++q)
+#pragma unroll
+          for (int jj = 0; jj < V_JG; ++jj)
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+              if (j0 + jj < CT) {
+                const uint4 av = afr[i][MxProds<P>::a[q]];
+                acc[i][j0 + jj] =
+                    mfma_bf16(*(const bf8_t*)&av, b[jj][MxProds<P>::b[q]], acc[i][j0 + jj]);
+              }
+      }
+    }
+    if (more) {
+      store_b(lds + ((ch + 1) & 1) * BSTAGE);
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) afr[i][p] = anx[i][p];
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: element e of tile (i, j) is operator row 4 (lane / 16) + e,
+  // column lane % 16 of the tile
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    if (i >= mtv) continue;
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      const int c = j * 16 + lr;
+      if (c >= nc) continue;
+      const bool im_row = c >= N;
+      const int jo = im_row ? c - N : c;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = (rt0 + i) * 16 + (lane >> 4) * 4 + e;
+        if (r >= nr) continue;
+        double val = (double)acc[i][j][e];
+        const int64_t pcol = row0 + r;
+        const int64_t off = (int64_t)w * o.sw + (int64_t)jo * o.sj + pcol;
+        if (mode == 1) {
+          val *= inv_n;
+          const int64_t soff = (int64_t)w * sum.sw + (int64_t)jo * sum.sj + pcol;
+          if (im_row) sum.im[soff] += val;
+          else sum.re[soff] += val;
+        }
+        if (im_row) o.im[off] = val;
+        else o.re[off] = val;
+      }
+    }
+  }
+}
+
+template <int CT, int P>
+hipError_t launch_mv_mx(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+                        hipStream_t st) {
+  constexpr int RT = CT <= 7 ? 3 : 2;   // registers: accumulators + fragments
+  const int TR_all = (s.M + 15) / 16;
+  const int nrb = (TR_all + MW * RT - 1) / (MW * RT);
+  const size_t lds = (size_t)2 * P * CT * 16 * M_PITCH * 2;
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec_mx<CT, P, RT>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
+  hipLaunchKernelGGL((k_matvec_mx<CT, P, RT>), dim3(s.W * nrb), dim3(MT_), lds, st, s.W, s.N, s.M,
+                     s.Kq, nrb, s.Ab, s.Ab_ps, v, o, mode, inv_n, sum);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_split(const double* in, int64_t R, int K, int64_t ld, int Kp, int P,
@@ -406,4 +632,30 @@ hipError_t launch_exchange_mx(SysDev& s, int W, const unsigned short* tb, int64_
   if (TC <= 7) return launch_mx<7, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
   if (TC <= 10) return launch_mx<10, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
   return launch_mx<13, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
+}
+
+hipError_t launch_split_op(SysDev& s, hipStream_t st) {
+  if (!s.Ab || s.op_pieces < 1 || s.op_pieces > 3) return hipErrorInvalidValue;
+  const int64_t R = (int64_t)s.W * s.M;
+  const int64_t n = R * s.Kq;
+  hipLaunchKernelGGL(k_split_op, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.A_re, s.A_im,
+                     R, s.M, s.Kq, s.op_pieces, s.Ab_ps, s.Ab);
+  return hipGetLastError();
+}
+
+hipError_t launch_matvec_mx(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+                            hipStream_t st) {
+  if (!s.Ab || 2 * s.N > 160) return hipErrorInvalidValue;
+  const int TC = (2 * s.N + 15) / 16;
+  if (s.op_pieces == 3) {
+    if (TC <= 4) return launch_mv_mx<4, 3>(s, v, o, mode, inv_n, sum, st);
+    if (TC <= 7) return launch_mv_mx<7, 3>(s, v, o, mode, inv_n, sum, st);
+    return launch_mv_mx<10, 3>(s, v, o, mode, inv_n, sum, st);
+  }
+  if (s.op_pieces == 2) {
+    if (TC <= 4) return launch_mv_mx<4, 2>(s, v, o, mode, inv_n, sum, st);
+    if (TC <= 7) return launch_mv_mx<7, 2>(s, v, o, mode, inv_n, sum, st);
+    return launch_mv_mx<10, 2>(s, v, o, mode, inv_n, sum, st);
+  }
+  return hipErrorInvalidValue;
 }
