@@ -74,6 +74,14 @@ struct SysDev {
   unsigned short* Ab = nullptr;
   int64_t Ab_ps = 0;
   int Kq = 0;
+  // BF16-split operator build: pieces of the Cholesky vectors transposed to
+  // [P][M M][Gp] (made once, three pieces) and of the field coefficients
+  // [P][2W][Gp] (per step), Gp = G padded to a multiple of 32
+  unsigned short* Ltb = nullptr;
+  int64_t Ltb_ps = 0;
+  unsigned short* avb = nullptr;
+  int64_t avb_ps = 0;
+  int Gp = 0;
   // tuned tile shape of the local-energy contraction (0 = occupancy model)
   int x_ga = 0, x_wb = 0;
   // tuned column blocks of the operator-orbital product (0 = default)
@@ -152,8 +160,11 @@ hipError_t launch_opbuild(SysDev& s, hipStream_t st);
 // sum += out (mode 1, a Taylor term), with the operator pieces in s.Ab.
 hipError_t launch_matvec_mx(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                             hipStream_t st);
-// Split the operator planes A_re / A_im into s.op_pieces pieces in s.Ab.
-hipError_t launch_split_op(SysDev& s, hipStream_t st);
+// Three pieces of L, transposed, into s.Ltb (once per system).
+hipError_t launch_split_lt(SysDev& s, hipStream_t st);
+// BF16-split operator build: pieces of the field coefficients, then the
+// operator pieces s.Ab straight from the piece products.
+hipError_t launch_opbuild_mx(SysDev& s, hipStream_t st);
 hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                           double* out_im, hipStream_t st);
 // Krylov exponential of the operator on every orbital: out = krylov_k(A, in);

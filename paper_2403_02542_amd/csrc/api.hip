@@ -888,6 +888,7 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   s.adj_ws_n = 0;
   s.coul_ws = nullptr;
   s.Ab = nullptr;
+  s.avb = nullptr;
   if (s.mx_pieces) s.mx_pieces = -1;  // pieces of L stay; Theta buffer re-made
   auto& own = s.walker_allocs;
   s.W = (int)n_walkers;
@@ -992,11 +993,24 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     if (energy_pieces(P->precision))
       TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], energy_pieces(P->precision)));
     ss[i]->op_pieces = op_pieces_of(P->precision);
-    if (ss[i]->op_pieces > 0 && !ss[i]->Ab) {
+    if (ss[i]->op_pieces > 0) {
       SysDev& s = *ss[i];
-      s.Kq = (2 * s.M + 31) / 32 * 32;
-      s.Ab_ps = (int64_t)s.W * s.M * s.Kq;
-      TRY(dalloc(ctx, s.walker_allocs, &s.Ab, (size_t)3 * s.Ab_ps));
+      s.Gp = (s.G + 31) / 32 * 32;
+      if (!s.Ab) {
+        s.Kq = (2 * s.M + 31) / 32 * 32;
+        s.Ab_ps = (int64_t)s.W * s.M * s.Kq;
+        TRY(dalloc(ctx, s.walker_allocs, &s.Ab, (size_t)3 * s.Ab_ps));
+        // the K padding (2M..Kq) of the operator pieces is never written
+        // again and must hold zeros
+        HIPCHK(hipMemsetAsync(s.Ab, 0, sizeof(unsigned short) * 3 * s.Ab_ps, ctx->stream));
+        s.avb_ps = (int64_t)2 * s.W * s.Gp;
+        TRY(dalloc(ctx, s.walker_allocs, &s.avb, (size_t)3 * s.avb_ps));
+      }
+      if (!s.Ltb) {
+        s.Ltb_ps = (int64_t)s.M * s.M * s.Gp;
+        TRY(dalloc(ctx, ctx->sys_allocs[sys_ids[i]], &s.Ltb, (size_t)3 * s.Ltb_ps));
+        HIPCHK(launch_split_lt(s, ctx->stream));
+      }
     }
     if (P->energy_every > 1 && !ss[i]->coul_ws) {
       SysDev& s = *ss[i];

@@ -155,25 +155,21 @@ __global__ __launch_bounds__(OBP::NT) void k_onebody(int WN, int M, int n_ct,
 
 // ------------------------------------------------------------ operator build
 // A_plane[w][pq] = sum_g a_plane[w][g] L[g][pq],  a = i sqrt(tau) (x - fbar)
+// (FP64; the BF16-split build is k_opbuild_mx).
 
-
-// Tile of the operator build for each engine (the BF16-split engine stages
-// four-k units and holds more fragments, so it takes a narrower tile).
-template <int PC>
 struct OpTile {
-  static constexpr int WR = 4, WC = 2, RT = 2, CT = PC == 0 ? 4 : 2;
+  static constexpr int WR = 4, WC = 2, RT = 2, CT = 4;
   static constexpr int ROWS = WR * RT * 16, COLS = WC * CT * 16, NT = WR * WC * 64;
 };
 
-template <int PC>
-__global__ __launch_bounds__(OpTile<PC>::NT) void k_opbuild(int W, int G, int64_t MM,
+__global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int64_t MM,
                                                      const double* __restrict__ a_re,
                                                      const double* __restrict__ a_im,
                                                      const double* __restrict__ L,
                                                      double* __restrict__ A_re,
                                                      double* __restrict__ A_im, int n_rt,
                                                      int n_ct) {
-  using T = OpTile<PC>;
+  using T = OpTile;
   extern __shared__ double smem[];
   int ct, rt;
   if (!xcd_swizzle(blockIdx.x, n_rt, n_ct, ct, rt)) return;
@@ -187,7 +183,7 @@ __global__ __launch_bounds__(OpTile<PC>::NT) void k_opbuild(int W, int G, int64_
     return rr < W ? a_re[(int64_t)rr * G + k] : a_im[(int64_t)(rr - W) * G + k];
   };
   auto gb = [&](int c, int k) { return L[(int64_t)k * MM + c0 + c]; };
-  pipe_run<T::WR, T::WC, T::RT, T::CT, PC, false, true>(G, nr, nc, ga, gb, smem, [&](int r, int c, double v) {
+  pipe_run<T::WR, T::WC, T::RT, T::CT, 0, false, true>(G, nr, nc, ga, gb, smem, [&](int r, int c, double v) {
     if (r < nr && c < nc) {
       const int rr = r0 + r;
       if (rr < W) A_re[(int64_t)rr * MM + c0 + c] = v;
@@ -590,13 +586,12 @@ hipError_t onebody_p(SysDev& s, const double* in_re, const double* in_im, double
   return hipGetLastError();
 }
 
-template <int PC>
-hipError_t opbuild_p(SysDev& s, hipStream_t st) {
-  using T = OpTile<PC>;
-  constexpr size_t lds = pipe_lds_bytes<T::WR, T::WC, T::RT, T::CT, PC>();
+hipError_t opbuild_fp64(SysDev& s, hipStream_t st) {
+  using T = OpTile;
+  constexpr size_t lds = pipe_lds_bytes<T::WR, T::WC, T::RT, T::CT, 0>();
   static bool lds_ok = false;
   if (!lds_ok) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild<PC>,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     lds_ok = true;
@@ -604,7 +599,7 @@ hipError_t opbuild_p(SysDev& s, hipStream_t st) {
   const int64_t MM = (int64_t)s.M * s.M;
   const int n_rt = (2 * s.W + T::ROWS - 1) / T::ROWS;
   const int n_ct = (int)((MM + T::COLS - 1) / T::COLS);
-  hipLaunchKernelGGL(k_opbuild<PC>, dim3(xcd_grid(n_ct, n_rt)), dim3(T::NT), lds, st, s.W, s.G,
+  hipLaunchKernelGGL(k_opbuild, dim3(xcd_grid(n_ct, n_rt)), dim3(T::NT), lds, st, s.W, s.G,
                      MM, s.av_re, s.av_im, s.L, s.A_re, s.A_im, n_rt, n_ct);
   return hipGetLastError();
 }
@@ -619,10 +614,8 @@ hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, d
 }
 
 hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
-  if (s.op_pieces == 0) return opbuild_p<0>(s, st);
-  const hipError_t e = s.op_pieces == 3 ? opbuild_p<3>(s, st) : opbuild_p<2>(s, st);
-  if (e != hipSuccess) return e;
-  return launch_split_op(s, st);   // pieces for the operator-orbital products
+  if (s.op_pieces == 0) return opbuild_fp64(s, st);
+  return launch_opbuild_mx(s, st);   // operator pieces for the BF16-split products
 }
 
 hipError_t launch_taylor(SysDev& s, int k, const double* in_re, const double* in_im,

@@ -7,9 +7,12 @@
 //  * k_exchange_mx: the local-energy contraction of k_exchange.hip with the
 //    T_g blocks formed from BF16-split (Psi_T^T L_g) and Theta; the N x N
 //    blocks are reduced in float64 exactly as in the FP64 kernel.
-//  * k_split_op / k_matvec_mx: the operator-orbital product A^w psi of the
-//    exponential with the operator split once per step and the orbitals
-//    split while they are staged.
+//  * k_split_lt / k_split_av / k_opbuild_mx: the operator build A^w =
+//    sum_g a_g^w L_g from pieces of L (split once, transposed) and of the
+//    field coefficients a (split per step), writing the operator's pieces.
+//  * k_matvec_mx: the operator-orbital product A^w psi of the exponential
+//    from those operator pieces, with the orbitals split while they are
+//    staged.
 #include "afq_device.h"
 #include "afq_internal.h"
 
@@ -374,22 +377,239 @@ hipError_t launch_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps, 
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- operator pieces
-// Ab[p][w M + r][k] = piece p of A_re[w][r][k] (k < M), of A_im[w][r][k - M]
-// (M <= k < 2M), 0 up to Kq.
-__global__ void k_split_op(const double* __restrict__ are, const double* __restrict__ aim,
-                           int64_t R, int M, int Kq, int P, int64_t piece_stride,
+// ---------------------------------------------------------------- operator build
+// Ltb[p][pq][g] = piece p of L[g][pq] (0 for g >= G): 64 x 64 tiles
+// transposed through LDS so that both the reads and the writes run along
+// memory.
+__global__ __launch_bounds__(256) void k_split_lt(const double* __restrict__ L, int G, int64_t MM,
+                                                  int Gp, int64_t piece_stride,
+                                                  unsigned short* __restrict__ out) {
+  __shared__ double t[64][65];
+  const int64_t pq0 = (int64_t)blockIdx.x * 64;
+  const int g0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int g = g0 + r;
+    const int64_t pq = pq0 + tx;
+    t[r][tx] = (g < G && pq < MM) ? L[(int64_t)g * MM + pq] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t pq = pq0 + r;
+    const int g = g0 + tx;
+    if (pq < MM && g < Gp) {
+      double x = t[tx][r];
+      for (int p = 0; p < 3; ++p) {
+        const unsigned short b = bf16_bits_rn((float)x);
+        out[p * piece_stride + pq * Gp + g] = b;
+        x -= (double)bf16_bits_to_f(b);
+      }
+    }
+  }
+}
+
+// avb[p][r][g]: pieces of the field coefficients, rows r < W the real plane
+// of walker r, rows W + w the imaginary plane; 0 for g >= G.
+__global__ void k_split_av(const double* __restrict__ are, const double* __restrict__ aim, int W,
+                           int G, int Gp, int P, int64_t piece_stride,
                            unsigned short* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= R * Kq) return;
-  const int64_t r = e / Kq;
-  const int k = (int)(e - r * Kq);
-  double x = k < M ? are[r * M + k] : (k < 2 * M ? aim[r * M + (k - M)] : 0.0);
+  if (e >= (int64_t)2 * W * Gp) return;
+  const int r = (int)(e / Gp), g = (int)(e - (int64_t)r * Gp);
+  double x = g < G ? (r < W ? are[(int64_t)r * G + g] : aim[(int64_t)(r - W) * G + g]) : 0.0;
   for (int p = 0; p < P; ++p) {
     const unsigned short b = bf16_bits_rn((float)x);
     out[p * piece_stride + e] = b;
     x -= (double)bf16_bits_to_f(b);
   }
+}
+
+// Tile: rows (plane, w) of the coefficients (256, loaded by each wave straight
+// into registers) times 208 columns pq of L (staged in LDS), K = Gp.  The
+// FP32 sums are the operator elements A_plane^w[p][q]; the epilogue splits
+// each into P pieces at Ab[piece][w M + p][plane M + q], the layout of the
+// operator-orbital product.  Tiles are dealt to the XCDs in contiguous
+// ranges, row blocks fastest, so the row blocks of one column block share
+// their L chunks in one L2.
+constexpr int O_CT = 13;
+
+template <int P>
+__global__ __launch_bounds__(MT_) void k_opbuild_mx(int W, int M, int Gp, int Kq, int n_rb,
+                                                    int n_tiles, int per_xcd,
+                                                    const unsigned short* __restrict__ avb,
+                                                    int64_t avb_ps,
+                                                    const unsigned short* __restrict__ Ltb,
+                                                    int64_t Ltb_ps, unsigned short* __restrict__ Ab,
+                                                    int64_t Ab_ps) {
+  extern __shared__ double smem[];
+  unsigned short* lds = (unsigned short*)smem;
+  constexpr int CT = O_CT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tile = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (tile >= n_tiles) return;
+  const int cb = tile / n_rb, rb = tile - cb * n_rb;
+  const int64_t MM = (int64_t)M * M;
+  const int64_t pq0 = (int64_t)cb * CT * 16;
+  const int R = 2 * W, r0 = rb * M_ROWS;
+  const int nr = min(M_ROWS, R - r0);
+  const int nc = (int)min((int64_t)CT * 16, MM - pq0);
+  const int TR = (nr + 15) >> 4;
+  const int rpw = (TR + MW - 1) / MW;
+  const int rt0 = wave * rpw;
+  const int mtv = max(0, min(rpw, TR - rt0));
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+
+  // ---- row operand: coefficient pieces straight from global memory
+  bool arow_ok[M_RT];
+  const unsigned short* aptr[M_RT];
+#pragma unroll
+  for (int i = 0; i < M_RT; ++i) {
+    const int r = (rt0 + i) * 16 + lr;
+    arow_ok[i] = (i < mtv) && (r < nr);
+    aptr[i] = avb + (int64_t)(r0 + (arow_ok[i] ? r : 0)) * Gp + lk;
+  }
+  uint4 afr[M_RT][P];
+  auto fetch_a = [&](int k0, uint4 (&dst)[M_RT][P]) {
+#pragma unroll
+    for (int i = 0; i < M_RT; ++i)
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        dst[i][p] = arow_ok[i] ? *(const uint4*)(aptr[i] + p * avb_ps + k0) : make_uint4(0, 0, 0, 0);
+  };
+
+  // ---- column operand: L pieces, staged in LDS [stage][p][col][M_PITCH]
+  constexpr int BROWS = CT * 16;
+  constexpr int BSTAGE = P * BROWS * M_PITCH;
+  constexpr int UNITS = BROWS * P * (M_KC / 8);
+  constexpr int PFU = (UNITS + MT_ - 1) / MT_;
+  uint4 pf[PFU];
+  auto fetch_b = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < PFU; ++i) {
+      const int u = tid + i * MT_;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (u < UNITS) {
+        const int k8 = u & 3, rp = u >> 2, p = rp / BROWS, c = rp - p * BROWS;
+        if (c < nc) v = *(const uint4*)(Ltb + p * Ltb_ps + (pq0 + c) * Gp + k0 + k8 * 8);
+      }
+      pf[i] = v;
+    }
+  };
+  auto store_b = [&](unsigned short* S) {
+#pragma unroll
+    for (int i = 0; i < PFU; ++i) {
+      const int u = tid + i * MT_;
+      if (u < UNITS) {
+        const int k8 = u & 3, rp = u >> 2, p = rp / BROWS, c = rp - p * BROWS;
+        *(uint4*)(S + ((size_t)p * BROWS + c) * M_PITCH + k8 * 8) = pf[i];
+      }
+    }
+  };
+
+  f4_t acc[M_RT][CT];
+#pragma unroll
+  for (int i = 0; i < M_RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+  // invalid row fragments and columns beyond nc hold zeros
+  const bool active = mtv > 0;
+  const int nchunk = Gp / M_KC;
+  fetch_a(0, afr);
+  fetch_b(0);
+  store_b(lds);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const unsigned short* Bs = lds + (ch & 1) * BSTAGE;
+    uint4 anx[M_RT][P];
+    const bool more = ch + 1 < nchunk;
+    if (more) {
+      fetch_a((ch + 1) * M_KC, anx);
+      fetch_b((ch + 1) * M_KC);
+    }
+    if (active) {
+#pragma unroll
+      for (int j0 = 0; j0 < CT; j0 += M_JG) {
+        bf8_t b[M_JG][P];
+#pragma unroll
+        for (int jj = 0; jj < M_JG; ++jj)
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+            if (j0 + jj < CT)
+              b[jj][p] = *(const bf8_t*)(Bs + ((size_t)p * BROWS + (j0 + jj) * 16 + lr) * M_PITCH + lk);
+#pragma unroll
+        for (int q = 0; q < MxProds<P>::N; ++q)
+#pragma unroll
+          for (int jj = 0; jj < M_JG; ++jj)
+#pragma unroll
+            for (int i = 0; i < M_RT; ++i)
+              if (j0 + jj < CT) {
+                const uint4 av = afr[i][MxProds<P>::a[q]];
+                acc[i][j0 + jj] =
+                    mfma_bf16(*(const bf8_t*)&av, b[jj][MxProds<P>::b[q]], acc[i][j0 + jj]);
+              }
+      }
+    }
+    if (more) {
+      store_b(lds + ((ch + 1) & 1) * BSTAGE);
+#pragma unroll
+      for (int i = 0; i < M_RT; ++i)
+#pragma unroll
+        for (int p = 0; p < P; ++p) afr[i][p] = anx[i][p];
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: element e of tile (i, j) is row 4 (lane / 16) + e, column
+  // lane % 16; each value goes out as its P pieces
+#pragma unroll
+  for (int i = 0; i < M_RT; ++i) {
+    if (i >= mtv) continue;
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      const int c = j * 16 + lr;
+      if (c >= nc) continue;
+      const int64_t pq = pq0 + c;
+      const int pr = (int)(pq / M), qc = (int)(pq - (int64_t)pr * M);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = (rt0 + i) * 16 + (lane >> 4) * 4 + e;
+        if (r >= nr) continue;
+        const int rg = r0 + r;
+        const bool im = rg >= W;
+        const int w = im ? rg - W : rg;
+        const int64_t off = ((int64_t)w * M + pr) * Kq + (im ? M : 0) + qc;
+        float x = acc[i][j][e];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const unsigned short b = bf16_bits_rn(x);
+          Ab[p * Ab_ps + off] = b;
+          x -= bf16_bits_to_f(b);
+        }
+      }
+    }
+  }
+}
+
+template <int P>
+hipError_t launch_opb_mx(SysDev& s, hipStream_t st) {
+  const int n_rb = (2 * s.W + M_ROWS - 1) / M_ROWS;
+  const int64_t MM = (int64_t)s.M * s.M;
+  const int64_t n_cb = (MM + O_CT * 16 - 1) / (O_CT * 16);
+  const int64_t n_tiles = n_cb * n_rb;
+  if (n_tiles > (1 << 28)) return hipErrorInvalidValue;
+  const int per_xcd = (int)((n_tiles + 7) / 8);
+  const size_t lds = (size_t)2 * P * O_CT * 16 * M_PITCH * 2;
+  static bool lds_ok = false;
+  if (!lds_ok) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild_mx<P>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    lds_ok = true;
+  }
+  hipLaunchKernelGGL(k_opbuild_mx<P>, dim3(per_xcd * 8), dim3(MT_), lds, st, s.W, s.M, s.Gp, s.Kq,
+                     n_rb, (int)n_tiles, per_xcd, s.avb, s.avb_ps, s.Ltb, s.Ltb_ps, s.Ab, s.Ab_ps);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- A^w psi
@@ -634,13 +854,22 @@ hipError_t launch_exchange_mx(SysDev& s, int W, const unsigned short* tb, int64_
   return launch_mx<13, 2>(s, W, tb, tb_ps, ell_re, ell_im, ex_re, ex_im, GA, WB, st);
 }
 
-hipError_t launch_split_op(SysDev& s, hipStream_t st) {
-  if (!s.Ab || s.op_pieces < 1 || s.op_pieces > 3) return hipErrorInvalidValue;
-  const int64_t R = (int64_t)s.W * s.M;
-  const int64_t n = R * s.Kq;
-  hipLaunchKernelGGL(k_split_op, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.A_re, s.A_im,
-                     R, s.M, s.Kq, s.op_pieces, s.Ab_ps, s.Ab);
+hipError_t launch_split_lt(SysDev& s, hipStream_t st) {
+  if (!s.Ltb || s.Gp < s.G || s.Gp % 32) return hipErrorInvalidValue;
+  const int64_t MM = (int64_t)s.M * s.M;
+  const dim3 grid((unsigned)((MM + 63) / 64), (unsigned)((s.Gp + 63) / 64));
+  hipLaunchKernelGGL(k_split_lt, grid, dim3(256), 0, st, s.L, s.G, MM, s.Gp, s.Ltb_ps, s.Ltb);
   return hipGetLastError();
+}
+
+hipError_t launch_opbuild_mx(SysDev& s, hipStream_t st) {
+  if (!s.Ab || !s.avb || !s.Ltb || s.op_pieces < 2 || s.op_pieces > 3) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)2 * s.W * s.Gp;
+  hipLaunchKernelGGL(k_split_av, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s.av_re,
+                     s.av_im, s.W, s.G, s.Gp, s.op_pieces, s.avb_ps, s.avb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return s.op_pieces == 3 ? launch_opb_mx<3>(s, st) : launch_opb_mx<2>(s, st);
 }
 
 hipError_t launch_matvec_mx(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
