@@ -46,11 +46,6 @@ AFQ_DEV cplx clog(cplx a) { return cplx{0.5 * log(cabs2(a)), atan2(a.im, a.re)};
 
 // ---------------------------------------------------------------- reductions
 
-AFQ_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 // Wave sum on the VALU's data-parallel lane moves (no LDS): pairs, quads,
 // half rows and rows of 16 lanes by quad permutations and mirrors, then rows
 // 0+1 and 2+3 by the broadcast of lane 15 into the next row, and the total
@@ -63,7 +58,7 @@ AFQ_DEV double dpp_move(double v) {
   const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, false);
   return __hiloint2double(h2, l2);
 }
-AFQ_DEV double wave_sum_dpp(double v) {
+AFQ_DEV double wave_sum(double v) {   // every lane of the wave must be active
   v += dpp_move<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
   v += dpp_move<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
   v += dpp_move<0x141, 0xf>(v);   // row_half_mirror

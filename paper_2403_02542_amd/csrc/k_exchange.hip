@@ -202,15 +202,15 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
             ++i;
           }
         }
-        xr = wave_sum_dpp(xr);
-        xi = wave_sum_dpp(xi);
+        xr = wave_sum(xr);
+        xi = wave_sum(xi);
         if (wave == gl % XW) {   // one wave adds up the diagonal (tr T)
           for (int d = lane; d < N; d += 64) {
             tr += T[d * ldt + d];
             ti += T[d * ldt + N + d];
           }
-          tr = wave_sum_dpp(tr);
-          ti = wave_sum_dpp(ti);
+          tr = wave_sum(tr);
+          ti = wave_sum(ti);
         }
         if (lane == 0) {
           double* rr = red + (gl * XW + wave) * 4;

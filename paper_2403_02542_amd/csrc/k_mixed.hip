@@ -291,15 +291,15 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
             ++i;
           }
         }
-        xr = wave_sum_dpp(xr);
-        xi = wave_sum_dpp(xi);
+        xr = wave_sum(xr);
+        xi = wave_sum(xi);
         if (wave == gl % MW) {   // one wave adds up the diagonal (tr T)
           for (int d = lane; d < N; d += 64) {
             tr += T[d * ldt + d];
             ti += T[d * ldt + N + d];
           }
-          tr = wave_sum_dpp(tr);
-          ti = wave_sum_dpp(ti);
+          tr = wave_sum(tr);
+          ti = wave_sum(ti);
         }
         if (lane == 0) {
           double* rr = red + (gl * MW + wave) * 4;
