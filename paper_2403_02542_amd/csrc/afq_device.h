@@ -69,6 +69,13 @@ AFQ_DEV double wave_sum(double v) {   // every lane of the wave must be active
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
   return __hiloint2double(hi, lo);
 }
+// Value of lane l (a compile-time constant after unrolling) in every lane,
+// through the scalar registers.
+AFQ_DEV double lane_bcast(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
 AFQ_DEV double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));

@@ -431,7 +431,8 @@ __global__ __launch_bounds__(256) void k_krylov_orth(int WN, int M, int kmax, in
 // out = beta * B_d exp(H_d) e_1 with d = dim <= 16.  exp(H_d) e_1 by s
 // Taylor substeps of 18 terms each, s = ceil(||H_d||_1 / 0.5), so that every
 // substep has a norm of at most 1/2.  Lane i < d owns row i of H_d and
-// component i of the vector; the vector is exchanged by lane shuffles.
+// component i of the vector; the vector is broadcast lane by lane through the
+// scalar registers.
 __global__ __launch_bounds__(256) void k_krylov_combine(int WN, int M, int kmax, int k,
                                                         const double* __restrict__ kb_re,
                                                         const double* __restrict__ kb_im,
@@ -473,7 +474,7 @@ __global__ __launch_bounds__(256) void k_krylov_combine(int WN, int M, int kmax,
       double nr = 0.0, ni = 0.0;
 #pragma unroll
       for (int l = 0; l < 16; ++l) {
-        const double u = __shfl(tr, l, 64), v = __shfl(ti, l, 64);
+        const double u = lane_bcast(tr, l), v = lane_bcast(ti, l);
         nr += hr[l] * u - hi[l] * v;
         ni += hr[l] * v + hi[l] * u;
       }
@@ -489,8 +490,8 @@ __global__ __launch_bounds__(256) void k_krylov_combine(int WN, int M, int kmax,
   double ur[16], ui[16];
 #pragma unroll
   for (int l = 0; l < 16; ++l) {
-    ur[l] = __shfl(yr, l, 64) * beta;
-    ui[l] = __shfl(yi, l, 64) * beta;
+    ur[l] = lane_bcast(yr, l) * beta;
+    ui[l] = lane_bcast(yi, l) * beta;
   }
   const double* br = kb_re + (int64_t)o * kmax * M;
   const double* bi = kb_im + (int64_t)o * kmax * M;
