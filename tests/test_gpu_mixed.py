@@ -188,3 +188,38 @@ def test_mixed_c1_both_exponentials(ctx, method, prec_name):
         assert errs.max() < E_TOL
     else:
         assert np.median(errs) < 1e-5 and np.percentile(errs, 95) < E_TOL
+
+
+@pytest.mark.parametrize("M,N", [(400, 20), (396, 9)])
+@pytest.mark.parametrize("method", ["krylov", "taylor"])
+def test_mixed_step_large_m(M, N, method):
+    """The BF16-split operator build and operator-orbital product beyond 384
+    orbitals (the product then takes two row blocks per walker), with a 2N
+    that leaves part of a column tile empty (N = 9): one MIXED step against
+    one FP64 step from the same walkers on the same fields.  The system
+    follows the recipe of the production shapes (couplings scaled by
+    1/sqrt(M), so the operator norm stays O(1)); the orbitals then keep the
+    accuracy they have at the production shape."""
+    import math
+    import torch
+    from paper_2403_02542_amd import afq
+    C.require_gpu()
+    s = 1.0 / math.sqrt(M)
+    case = C.Case.random(M, N, 64, seed=11, sigma_h=0.1 * s, sigma_A=0.05 * s)
+    nw = 16
+    em = afq.EXP_KRYLOV if method == "krylov" else afq.EXP_TAYLOR
+    res = {}
+    for prec in (afq.PREC_FP64, afq.PREC_MIXED):
+        c = afq.Context(0)
+        sid = case.gpu(c, nw)
+        x = C.to_dev(W.fields(0, 0, 0, nw, case.G))
+        c.propagate_batch(sid, tau=0.05, n_steps=1, exp_method=em, exp_order=8,
+                          reorth_every=1, step0=0, fields=x, precision=prec)
+        torch.cuda.synchronize()
+        res[prec] = c.get_walkers(sid)
+        c.close()
+    ref, mx = res[afq.PREC_FP64], res[afq.PREC_MIXED]
+    err = max(C.rel(mx["phi"][w], ref["phi"][w]) for w in range(nw))
+    print(f"M={M} N={N} {method}: MIXED orbitals max rel. {err:.2e}", flush=True)
+    assert np.all(np.isfinite(mx["phi"]))
+    assert err < 1e-6
