@@ -77,6 +77,11 @@ struct SysDev {
   // BF16-split operator build: pieces of the Cholesky vectors transposed to
   // [P][M M][Gp] (made once, three pieces) and of the field coefficients
   // [P][2W][Gp] (per step), Gp = G padded to a multiple of 32
+  // 8 x 16 blocks (p0, q0) of the operator on or above its diagonal, for the
+  // FP64 build (the operator is symmetric; device table, made before the
+  // first step)
+  int2* op_blk = nullptr;
+  int n_op_blk = 0;
   unsigned short* Ltb = nullptr;
   int64_t Ltb_ps = 0;
   unsigned short* avb = nullptr;
@@ -156,6 +161,10 @@ struct VecOut {
   int64_t sw, sj;
 };
 hipError_t launch_opbuild(SysDev& s, hipStream_t st);
+// Origins of the R x 16 blocks of an M x M symmetric matrix that hold an
+// element on or above the diagonal, row blocks outermost.
+void op_blocks(int M, int R, std::vector<int2>& out);
+constexpr int kOpRowsFP64 = 8;
 // BF16-split operator-orbital product out = A v (mode 0) or out = A v / n,
 // sum += out (mode 1, a Taylor term), with the operator pieces in s.Ab.
 hipError_t launch_matvec_mx(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,

@@ -207,6 +207,20 @@ afq_status ensure_krylov(afq_ctx* ctx, int32_t sid, SysDev& s, int k) {
 }
 
 // BF16 pieces of the half-rotated blocks and a Theta piece buffer.
+// Block table of the symmetric FP64 operator build (made once per system,
+// on the host, before any step is captured).
+afq_status ensure_op_blocks(afq_ctx* ctx, int32_t sid, SysDev& s) {
+  if (s.op_blk) return AFQ_OK;
+  std::vector<int2> b;
+  op_blocks(s.M, kOpRowsFP64, b);
+  int2* d = nullptr;
+  TRY(dalloc(ctx, ctx->sys_allocs[sid], &d, b.size()));
+  HIPCHK(hipMemcpy(d, b.data(), sizeof(int2) * b.size(), hipMemcpyHostToDevice));
+  s.op_blk = d;
+  s.n_op_blk = (int)b.size();
+  return AFQ_OK;
+}
+
 afq_status ensure_mixed(afq_ctx* ctx, int32_t sid, SysDev& s, int pieces) {
   if (s.mx_pieces == pieces && s.Lxb && s.thb) return AFQ_OK;
   auto& own = ctx->sys_allocs[sid];
@@ -993,6 +1007,7 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     if (energy_pieces(P->precision))
       TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], energy_pieces(P->precision)));
     ss[i]->op_pieces = op_pieces_of(P->precision);
+    TRY(ensure_op_blocks(ctx, sys_ids[i], *ss[i]));
     if (ss[i]->op_pieces > 0) {
       SysDev& s = *ss[i];
       s.Gp = (s.G + 31) / 32 * 32;

@@ -4,6 +4,8 @@
 //  * the operator build A^w = i sqrt(tau) sum_g (x_g - fbar_g) L_g (Eq. heffTOT),
 //  * the operator-orbital product A^w psi that every exponential method
 //    repeats k times (Sec. IV), with the Taylor and Krylov drivers.
+#include <algorithm>
+
 #include "afq_device.h"
 #include "afq_internal.h"
 
@@ -154,40 +156,52 @@ __global__ __launch_bounds__(OBP::NT) void k_onebody(int WN, int M, int n_ct,
 }
 
 // ------------------------------------------------------------ operator build
-// A_plane[w][pq] = sum_g a_plane[w][g] L[g][pq],  a = i sqrt(tau) (x - fbar)
-// (FP64; the BF16-split build is k_opbuild_mx).
+// A_plane[w][p][q] = sum_g a_plane[w][g] L[g][p][q],  a = i sqrt(tau) (x - fbar)
+// (FP64; the BF16-split build is k_opbuild_mx).  A is symmetric, so only
+// the column blocks of (p, q) that hold an element on or above the diagonal
+// are formed (the packed triangle, M(M+1)/2 of the M^2 columns, padded to
+// whole blocks); each element with q >= p is written to A[p][q] and A[q][p].
 
 struct OpTile {
   static constexpr int WR = 4, WC = 2, RT = 2, CT = 4;
   static constexpr int ROWS = WR * RT * 16, COLS = WC * CT * 16, NT = WR * WC * 64;
 };
+static_assert(OpTile::COLS == kOpRowsFP64 * 16, "a column tile is one 8 x 16 block of (p, q)");
 
-__global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int64_t MM,
+__global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int M,
                                                      const double* __restrict__ a_re,
                                                      const double* __restrict__ a_im,
                                                      const double* __restrict__ L,
                                                      double* __restrict__ A_re,
-                                                     double* __restrict__ A_im, int n_rt,
+                                                     double* __restrict__ A_im,
+                                                     const int2* __restrict__ blk, int n_rt,
                                                      int n_ct) {
   using T = OpTile;
   extern __shared__ double smem[];
   int ct, rt;
   if (!xcd_swizzle(blockIdx.x, n_rt, n_ct, ct, rt)) return;
   const int r0 = rt * T::ROWS;
-  const int64_t c0 = (int64_t)ct * T::COLS;
+  const int2 b0 = blk[ct];
+  const int p0 = b0.x, q0 = b0.y;
+  const int64_t MM = (int64_t)M * M;
   const int R = 2 * W;
   const int nr = min(T::ROWS, R - r0);
-  const int nc = (int)min((int64_t)T::COLS, MM - c0);
   auto ga = [&](int r, int k) {
     const int rr = r0 + r;
     return rr < W ? a_re[(int64_t)rr * G + k] : a_im[(int64_t)(rr - W) * G + k];
   };
-  auto gb = [&](int c, int k) { return L[(int64_t)k * MM + c0 + c]; };
-  pipe_run<T::WR, T::WC, T::RT, T::CT, 0, false, true>(G, nr, nc, ga, gb, smem, [&](int r, int c, double v) {
-    if (r < nr && c < nc) {
+  auto gb = [&](int c, int k) {
+    const int p = p0 + (c >> 4), q = q0 + (c & 15);
+    return (p < M && q < M) ? L[(int64_t)k * MM + (int64_t)p * M + q] : 0.0;
+  };
+  pipe_run<T::WR, T::WC, T::RT, T::CT, 0, false, true>(G, nr, T::COLS, ga, gb, smem,
+                                                        [&](int r, int c, double v) {
+    const int p = p0 + (c >> 4), q = q0 + (c & 15);
+    if (r < nr && p < M && q < M && q >= p) {
       const int rr = r0 + r;
-      if (rr < W) A_re[(int64_t)rr * MM + c0 + c] = v;
-      else A_im[(int64_t)(rr - W) * MM + c0 + c] = v;
+      double* A = rr < W ? A_re + (int64_t)rr * MM : A_im + (int64_t)(rr - W) * MM;
+      A[(int64_t)p * M + q] = v;
+      if (q != p) A[(int64_t)q * M + p] = v;
     }
   });
 }
@@ -597,11 +611,11 @@ hipError_t opbuild_fp64(SysDev& s, hipStream_t st) {
     if (e != hipSuccess) return e;
     lds_ok = true;
   }
-  const int64_t MM = (int64_t)s.M * s.M;
+  if (!s.op_blk || s.n_op_blk < 1) return hipErrorInvalidValue;
   const int n_rt = (2 * s.W + T::ROWS - 1) / T::ROWS;
-  const int n_ct = (int)((MM + T::COLS - 1) / T::COLS);
+  const int n_ct = s.n_op_blk;
   hipLaunchKernelGGL(k_opbuild, dim3(xcd_grid(n_ct, n_rt)), dim3(T::NT), lds, st, s.W, s.G,
-                     MM, s.av_re, s.av_im, s.L, s.A_re, s.A_im, n_rt, n_ct);
+                     s.M, s.av_re, s.av_im, s.L, s.A_re, s.A_im, s.op_blk, n_rt, n_ct);
   return hipGetLastError();
 }
 
@@ -612,6 +626,13 @@ hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, d
   if (s.op_pieces == 3) return onebody_p<3>(s, in_re, in_im, out_re, out_im, st);
   if (s.op_pieces == 2) return onebody_p<2>(s, in_re, in_im, out_re, out_im, st);
   return onebody_p<0>(s, in_re, in_im, out_re, out_im, st);
+}
+
+void op_blocks(int M, int R, std::vector<int2>& out) {
+  out.clear();
+  for (int p0 = 0; p0 < M; p0 += R)
+    for (int q0 = 0; q0 < M; q0 += 16)
+      if (std::min(M, q0 + 16) - 1 >= p0) out.push_back(make_int2(p0, q0));
 }
 
 hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
