@@ -8,7 +8,7 @@ vectors, 512 walkers, Krylov dimension 10, QR every 5 steps, tau = 0.05.
 Inputs are seeded synthetic Hamiltonians (no molecular integrals are
 available); all inputs are resident in HBM before the timed region.
 
-Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: this build
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: the library
 runs on one GPU.
 """
 import argparse
@@ -436,7 +436,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (got --gpus {args.gpus}); "
               "walkers shard trivially across GPUs but no multi-GPU path is built.",
               file=sys.stderr)
         sys.exit(2)
