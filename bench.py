@@ -47,7 +47,7 @@ def exchange_flops_per_walker(M, N, G):
 def step_flops_per_walker(M, N, G, k, reorth_every):
     """Algorithmic flops of one walker step (the production-shape count)."""
     ex = exchange_flops_per_walker(M, N, G)
-    build = 4.0 * G * M * M                 # A = sum_g a_g L_g, full complex M x M
+    build = 2.0 * G * M * (M + 1)           # A = sum_g a_g L_g, symmetric: packed triangle
     matvec = 8.0 * k * M * M * N            # k complex operator-orbital products
     onebody = 2 * 4.0 * M * M * N           # two real x complex half-steps
     arnoldi = 8.0 * M * N * (k * k + 2 * k)
