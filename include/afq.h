@@ -98,7 +98,7 @@ typedef struct {
   int32_t exp_method;    /* AFQ_EXP_KRYLOV or AFQ_EXP_TAYLOR                   */
   int32_t exp_order;     /* k: Krylov dimension / Taylor order (1..16)            */
   int32_t reorth_every;  /* QR after global step t when (t+1) % reorth_every == 0 */
-  int32_t precision;     /* AFQ_PREC_FP64, AFQ_PREC_MIXED or AFQ_PREC_MIXED_FAST   */
+  int32_t precision;     /* AFQ_PREC_*: FP64, MIXED, MIXED_FAST or MIXED_ENERGY  */
   int32_t n_steps;       /* steps to run                                         */
   int32_t energy_every;  /* local energy every this many steps (and at the last);
                             0 is read as 1.  Other steps form only the Coulomb
@@ -140,7 +140,13 @@ enum { AFQ_SCHED_AUTO = 0, AFQ_SCHED_SERIAL = 1, AFQ_SCHED_STREAMS = 2, AFQ_SCHE
  * inside the loop.  A walker whose new overlap or Green's function is not
  * finite, or whose reorthonormalisation fails (numerically rank-deficient
  * orbitals), is frozen: its state is held, its weight set to 0 and it is
- * counted (not an error; see afq_get_counters). */
+ * counted (not an error; see afq_get_counters).  Workspace the call needs is
+ * allocated by the library on first use and owned by the context: the
+ * Krylov basis, the block table of the operator build and, for MIXED and
+ * MIXED_FAST, three BF16 pieces of L per system (6 Gp M^2 bytes, Gp = G
+ * rounded up to 32, made once) and of the operator per walker set
+ * (6 W M Kq bytes, Kq = 2M rounded up to 32); a failed allocation returns
+ * AFQ_ENOMEM. */
 afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys,
                                const afq_prop_params* params);
 
