@@ -191,6 +191,23 @@ def test_r1_shifted_hamiltonian_identity():
     assert np.abs(H - rhs).max() < 1e-12
 
 
+def test_p4_operator_complex_symmetric():
+    """interaction_operator: with symmetric L_g and complex shifts the
+    operator is complex symmetric, A = A^T (not Hermitian), so its upper
+    triangle mirrored is A itself, exactly -- the property the GPU's operator
+    build relies on when it forms only the blocks on or above the diagonal."""
+    M, N, G = 7, 3, 5
+    h, L = _rand_system(M, G, seed=3)
+    p = O.prepare(h, L, 0.0, _trial(M, N, 3), tau=0.05)
+    rng = np.random.default_rng(9)
+    x = rng.normal(size=G)
+    fbar = 0.3 * (rng.normal(size=G) + 1j * rng.normal(size=G))
+    A, _, _ = O.interaction_operator(p, x, fbar)
+    assert np.array_equal(A, A.T)
+    assert not np.allclose(A, A.conj().T)
+    assert np.array_equal(np.triu(A) + np.triu(A, 1).T, A)
+
+
 @pytest.mark.parametrize("method", [O.EXP_KRYLOV, O.EXP_TAYLOR])
 def test_p4_importance_sampled_step_expectation(method):
     """With one Cholesky vector the HS transform is exact.  The Gauss-Hermite
