@@ -17,7 +17,11 @@ Readings of the paper where it is silent or ambiguous are marked "Reading:".
 
 Parity pins: every public function is pinned by a test in tests/ against a
 brute-force Fock-space computation, a closed form, a textbook routine or an
-invariant (see the test module docstrings).  No function here is unpinned.
+invariant (see the test module docstrings): the weighted estimator of `run`
+by Fock-space ratios and energies of distinct walkers, the phase convention
+of `reorthonormalise` by Gram-Schmidt on inputs whose raw LAPACK factor has
+negative diagonal entries.  The phaseless bias of a whole trajectory has no
+exact value to pin against (parity of trajectories is checked step by step).
 """
 from __future__ import annotations
 
@@ -297,11 +301,23 @@ def phaseless_factor(p: Prepared, e_h: complex, dtheta: float) -> float:
     """exp(-tau (Re E_H - E0)) max(0, cos dtheta)   (Eq. phaseless), with the
     reweighting cap of Sec. V.B: a factor of 10 or more becomes 0 (Reading:
     the cap applies to the magnitude, before the cosine)."""
+    return phaseless_parts(p, e_h, dtheta)[0]
+
+
+def phaseless_parts(p: Prepared, e_h: complex, dtheta: float):
+    """(factor, rule): the factor of `phaseless_factor` and which rule, if
+    any, made it zero: "reweight_cap" (Sec. V.B) or "phase" (cos dtheta <= 0,
+    Eq. phaseless); "" otherwise."""
     arg = -p.tau * (e_h.real - p.e0)
     m = math.exp(arg) if arg < 700.0 else math.inf
+    rule = ""
     if not m < 10.0:
         m = 0.0
-    return m * max(0.0, math.cos(dtheta))
+        rule = "reweight_cap"
+    c = math.cos(dtheta)
+    if c <= 0.0 and rule == "":
+        rule = "phase"
+    return m * max(0.0, c), rule
 
 
 # --------------------------------------------------------------------------
@@ -339,6 +355,7 @@ class StepInfo:
     log_i: complex
     n_capped_f: int
     f: np.ndarray
+    zeroed_by: str = ""       # rule that set a nonzero weight to 0 this step
 
 
 def init_walker(p: Prepared, phi0=None) -> Walker:
@@ -372,11 +389,15 @@ def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
         dead = Walker(wk.phi, wk.logdet, wk.theta, 0.0, False)
         e = local_energy(p, dead.phi, dead.theta)
         return dead, StepInfo(e, capped_energy(e, p.e0, 2 * p.N, p.tau), 0j,
-                              0.0, log_i, int(np.sum(fbar == 0)), f)
+                              0.0, log_i, int(np.sum(fbar == 0)), f,
+                              "frozen" if wk.weight != 0.0 else "")
     log_ratio = 2.0 * (logdet - wk.logdet) + s_mf
     e_h = hybrid_energy(p, log_ratio, log_i)
     dtheta = float(log_ratio.imag)
-    weight = wk.weight * phaseless_factor(p, e_h, dtheta)
+    factor, rule = phaseless_parts(p, e_h, dtheta)
+    weight = wk.weight * factor
+    if wk.weight == 0.0:
+        rule = ""
     if reorth:
         phi, logr = reorthonormalise(phi)
         logdet = logdet - logr
@@ -385,7 +406,7 @@ def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
     n_capped = int(np.sum(np.abs(f) >= 1.0))
     return (Walker(phi, logdet, theta, weight, True),
             StepInfo(e, capped_energy(e, p.e0, 2 * p.N, p.tau), e_h, dtheta,
-                     log_i, n_capped, f))
+                     log_i, n_capped, f, rule))
 
 
 def reorth_due(step: int, every: int) -> bool:
@@ -421,6 +442,7 @@ def run(p: Prepared, walkers, fields_of_step, n_steps: int, method: int,
             "dtheta": np.array([i.dtheta for i in infos]),
             "n_capped_f": np.array([i.n_capped_f for i in infos]),
             "f": np.array([i.f for i in infos]),
+            "zeroed_by": [i.zeroed_by for i in infos],
             "estimator": (float(np.sum(wts * ec)), float(np.sum(wts))),
         })
     return walkers, hist

@@ -310,6 +310,105 @@ def test_p8_right_multiplication_invariance():
     assert np.all(np.abs(np.diag(Rq).imag) < 1e-13) and np.all(np.diag(Rq).real > 0)
 
 
+def _gram_schmidt(phi):
+    """Textbook classical Gram-Schmidt with reorthogonalisation: the unique
+    Q with Q^H Q = I and Q^H phi upper triangular with a real positive
+    diagonal (written out column by column, independent of LAPACK)."""
+    M, N = phi.shape
+    Q = np.zeros((M, N), dtype=complex)
+    for j in range(N):
+        v = phi[:, j].astype(complex)
+        for _ in range(2):
+            for i in range(j):
+                v = v - np.vdot(Q[:, i], v) * Q[:, i]
+        Q[:, j] = v / np.linalg.norm(v)
+    return Q
+
+
+def test_p8_qr_phase_convention_against_gram_schmidt():
+    """reorthonormalise returns the unique Q whose R = Q^H Phi has a real
+    positive diagonal (Gram-Schmidt), and sum log R_jj = 1/2 log det(Phi^H Phi).
+    The inputs include -Phi and column-scaled copies, so that LAPACK's own
+    factor has negative (or, for the phases, different) diagonal entries in
+    at least one case and the phase fix is exercised."""
+    M, N = 9, 4
+    phi = _trial(M, N, 77) + 0.4 * _rand_walker(M, N, 77)
+    rng = np.random.default_rng(5)
+    ph = np.exp(1j * rng.uniform(-math.pi, math.pi, size=N))
+    cases = [phi, -phi, phi * ph[None, :], phi * np.array([1, -1, 1, -1])[None, :]]
+    raw_negative = 0
+    for X in cases:
+        _, Rraw = np.linalg.qr(X)
+        raw_negative += int(np.any(np.diag(Rraw).real < 0))
+        Q, logr = O.reorthonormalise(X)
+        assert np.abs(Q - _gram_schmidt(X)).max() < 1e-12
+        R = Q.conj().T @ X
+        assert np.abs(np.tril(R, -1)).max() < 1e-12
+        assert np.all(np.abs(np.diag(R).imag) < 1e-13) and np.all(np.diag(R).real > 0)
+        _, ld = np.linalg.slogdet(X.conj().T @ X)
+        assert abs(logr - 0.5 * ld) < 1e-12
+    assert raw_negative >= 2   # the pin is not vacuous
+
+
+def test_r12_reorthonormalisation_schedule():
+    """Reading of the schedule: QR after global step t when (t + 1) % r == 0.
+    With r = 3 the orbitals are orthonormal after steps t = 2 and 5 only."""
+    M, N, G = 8, 3, 4
+    h, L = _rand_system(M, G, 13, scale=0.1)
+    psi = _trial(M, N, 13)
+    p = O.prepare(h, L, 0.0, psi, 0.1)
+    wks = [O.init_walker(p)]
+    rng = np.random.default_rng(1)
+    xs = rng.normal(size=(6, 1, G))
+    ortho = []
+    for t in range(6):
+        wks, _ = O.run(p, wks, lambda s: xs[s], 1, O.EXP_TAYLOR, 6, 3, step0=t)
+        phi = wks[0].phi
+        ortho.append(bool(np.abs(phi.conj().T @ phi - np.eye(N)).max() < 1e-12))
+    assert ortho == [False, False, True, False, False, True]
+
+
+def test_p14_weighted_estimator_bruteforce():
+    """run's per-step estimator (sum_w W E_L, sum_w W) of Sec. II.A, pinned
+    with L = 0 where every factor has a closed form in Fock space: the step
+    is exp(-tau h) exactly, so W_w = |R_w| e^{tau (E0 - e_core)}
+    max(0, cos arg R_w) with R_w = <Psi_T|e^{-tau H}|Phi_w>/<Psi_T|Phi_w>,
+    and E_L^w = <Psi_T|H|Phi'_w>/<Psi_T|Phi'_w>, all by brute force for three
+    walkers with distinct weights and energies, over two steps."""
+    M, N = 4, 2
+    h, _ = _rand_system(M, 1, 17)
+    L = np.zeros((1, M, M))
+    psi = _trial(M, N, 17)
+    tau, e_core = 0.05, 0.3
+    p = O.prepare(h, L, e_core, psi, tau)
+    phis = [psi + s * _rand_walker(M, N, 17 + i) for i, s in enumerate((0.1, 0.25, 0.4))]
+    wks = [O.init_walker(p, ph) for ph in phis]
+    _, hist = O.run(p, wks, lambda t: np.zeros((3, 1)), 2, O.EXP_KRYLOV, 4, 0)
+    H = fock.hamiltonian(h, L, e_core).toarray()
+    U = scipy.linalg.expm(-tau * fock.one_body(h, M).toarray())
+    t = fock.determinant(psi.astype(complex))
+    e0 = (np.vdot(t, H @ t) / np.vdot(t, t)).real
+    d = O.energy_window(2 * N, tau)
+    W = np.ones(3)
+    vs = [fock.determinant(ph) for ph in phis]
+    for s in range(2):
+        E = np.empty(3)
+        for w in range(3):
+            v1 = U @ vs[w]
+            R = np.vdot(t, v1) / np.vdot(t, vs[w])
+            m = abs(R) * math.exp(tau * (e0 - e_core))
+            assert m < 10.0
+            W[w] *= m * max(0.0, math.cos(np.angle(R)))
+            E[w] = (np.vdot(t, H @ v1) / np.vdot(t, v1)).real
+            assert abs(E[w] - e0) < d            # inside the energy window
+            vs[w] = v1
+        assert np.ptp(W) > 1e-3 and np.ptp(E) > 1e-3   # distinct walkers
+        got = hist[s]["estimator"]
+        assert abs(got[1] - W.sum()) < 1e-12 * W.sum()
+        assert abs(got[0] - (W * E).sum()) < 1e-11 * abs((W * E).sum())
+        assert np.abs(hist[s]["weight"] - W).max() < 1e-12
+
+
 # ---------------------------------------------------------------- P-10 / P-11
 
 def test_p10_small_tau_limit_no_interaction():
