@@ -18,6 +18,7 @@ from .generate import (  # noqa: F401
     Hamiltonian,
     UnevenBatch,
     WorkloadConfig,
+    comb_uniform,
     fields,
     hamiltonian,
     make_system,

@@ -18,6 +18,8 @@ Recipe (stated once here, used everywhere):
   Each 64-bit word x gives u = ((x >> 11) + 1) * 2^-53 in (0, 1]; the pairs
   (u0, u1) and (u2, u3) of a block give, by the Box-Muller transform,
   fields g, g+1 and g+2, g+3 of that walker.
+* Population-control uniforms: the same generator under the key
+  (seed, system id + 2^32), counter = step; u = (x >> 11) 2^-53 in [0, 1).
 """
 from __future__ import annotations
 
@@ -133,6 +135,17 @@ def fields(seed: int, sys_id: int, step: int, n_walkers: int,
     z[..., 0::2] = r * np.cos(th)
     z[..., 1::2] = r * np.sin(th)
     return z.reshape(n_walkers, 4 * nb)[:, :n_chol].copy()
+
+
+def comb_uniform(seed: int, sys_id: int, step: int) -> float:
+    """The uniform number u in [0, 1) of a population-control step: word 0
+    of the Philox4x64-10 block of counter value step + 1 (numpy's counter
+    convention, as for the fields) under the key (seed, sys_id + 2^32), a key
+    the fields never use; u = (x >> 11) 2^-53."""
+    bitgen = np.random.Philox(key=np.array([seed, sys_id + (1 << 32)], dtype=np.uint64),
+                              counter=step)
+    x = bitgen.random_raw(4)[0]
+    return float(int(x) >> 11) * 2.0**-53
 
 
 def make_system(cfg: WorkloadConfig, trial_iters: int = 10):

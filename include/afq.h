@@ -104,7 +104,10 @@ typedef struct {
                             0 is read as 1.  Other steps form only the Coulomb
                             vector the next force bias needs, a ~100x cheaper
                             product than the local-energy contraction          */
-  double e0;             /* energy shift E0; NaN = trial energy (fixed)          */
+  double e0;             /* energy shift E0 of Eq. (imag_prop): a value sets the
+                            system's E0 and clears its update history; NaN keeps
+                            the system's current E0 (the trial energy E_L(Psi_T)
+                            after afq_init_walkers, unless updates moved it)    */
   uint64_t seed;         /* Philox key word 0 (word 1 is the system id)          */
   uint64_t step0;        /* global index of the first step (RNG counter, QR)     */
   const double* fields;  /* optional DEVICE array [n_steps][W][n_chol] of N(0,1)
@@ -113,6 +116,19 @@ typedef struct {
                             (sum_w W E_L capped, sum_w W) per step               */
   int32_t schedule;      /* AFQ_SCHED_*: how the steps of several systems are
                             issued (results are the same for every schedule)     */
+  int32_t e0_window;     /* 0: E0 stays fixed.  1..64: after every measured step
+                            E0 becomes the mean of the last e0_window per-step
+                            estimates sum W E_L / sum W that had sum W > 0 (the
+                            "best estimate" reading of Sec. II.A); a step with
+                            sum W = 0 leaves E0 unchanged                        */
+  int32_t pop_every;     /* 0: no population control (the paper describes none).
+                            > 0: after global step t with (t+1) % pop_every == 0,
+                            comb resampling by weight: with T = sum_w W_w and
+                            running sums C_i, slot j copies walker
+                            min{i : C_i > (j + u) T / W}, u in [0, 1) from
+                            Philox4x64-10 key (seed, sys_id + 2^32), counter
+                            t + 1, word 0, u = (x >> 11) 2^-53; every copy gets
+                            weight 1; T = 0 leaves the walkers alone             */
 } afq_prop_params;
 
 /* Schedules of afq_propagate_batch.
@@ -197,10 +213,16 @@ afq_status afq_set_walkers(afq_ctx* ctx, int32_t sys_id, const void* phi,
 afq_status afq_fill_fields(afq_ctx* ctx, uint64_t seed, uint64_t sys_id, uint64_t step,
                            int64_t n_walkers, int64_t n_chol, double* out_dev);
 
-/* Per-system diagnostics of the last afq_propagate_batch call (synchronises):
- * out[0] live walkers at the last measured step, out[1] capped force-bias
- * components, out[2] Krylov happy breakdowns, out[3] walkers frozen. */
-afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4);
+/* Per-system diagnostics of the last afq_propagate_batch call (synchronises),
+ * the first n (1..5) of: out[0] walkers not frozen at the last measured
+ * step, out[1] capped force-bias components, out[2] Krylov happy
+ * breakdowns, out[3] walkers frozen, out[4] walkers with weight W > 0 at
+ * the last measured step (0 means the population is extinct: the estimator
+ * sum W is 0). */
+afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out, int32_t n);
+
+/* Current E0 of a system (synchronises): the value the next step uses. */
+afq_status afq_get_e0(afq_ctx* ctx, int32_t sys_id, double* e0_out);
 
 /* Per-phase timing with HIP events on the context stream.  While enabled,
  * afq_propagate_batch records an event pair around every phase of every
@@ -209,7 +231,7 @@ afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4);
 enum {
   AFQ_PH_FIELDS = 0, AFQ_PH_FORCE_BIAS, AFQ_PH_OPBUILD, AFQ_PH_ONEBODY, AFQ_PH_EXPONENTIAL,
   AFQ_PH_OVERLAP, AFQ_PH_WEIGHT, AFQ_PH_QR, AFQ_PH_EXCHANGE, AFQ_PH_ENERGY, AFQ_PH_COULOMB,
-  AFQ_PH_COUNT
+  AFQ_PH_POPCTL, AFQ_PH_COUNT
 };
 afq_status afq_profile(afq_ctx* ctx, int enable);
 afq_status afq_profile_read(afq_ctx* ctx, double* ms_out, int64_t* launches_out, int n);

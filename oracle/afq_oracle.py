@@ -415,12 +415,17 @@ def reorth_due(step: int, every: int) -> bool:
 
 
 def run(p: Prepared, walkers, fields_of_step, n_steps: int, method: int,
-        k: int, reorth_every: int, step0: int = 0):
+        k: int, reorth_every: int, step0: int = 0, e0_state: E0State = None,
+        pop_every: int = 0, comb_u=None):
     """Propagate a list of walkers; fields_of_step(t) -> (W, G) array.
 
     Returns (walkers, history) where history[s] holds per-walker arrays of
     e_loc, weight, e_capped and the estimator (sum_w W E_L, sum_w W)
-    (Sec. II.A, weighted energy of step k)."""
+    (Sec. II.A, weighted energy of step k).  With e0_state, p.e0 follows
+    `update_e0` after every step; with pop_every > 0 the population is
+    comb-resampled after the estimator of every pop_every-th global step,
+    comb_u(t) giving the step's uniform number (history[s]["comb"] holds
+    the source indices)."""
     hist = []
     for s in range(n_steps):
         t = step0 + s
@@ -444,8 +449,85 @@ def run(p: Prepared, walkers, fields_of_step, n_steps: int, method: int,
             "f": np.array([i.f for i in infos]),
             "zeroed_by": [i.zeroed_by for i in infos],
             "estimator": (float(np.sum(wts * ec)), float(np.sum(wts))),
+            "e0": p.e0,
+            "comb": None,
         })
+        if e0_state is not None:
+            p.e0 = update_e0(e0_state, hist[-1]["estimator"])
+        if pop_control_due(t, pop_every):
+            src = comb_resample(wts, comb_u(t))
+            if src is not None:
+                walkers = [dataclasses.replace(walkers[i], weight=1.0) for i in src]
+                hist[-1]["comb"] = src
     return walkers, hist
+
+
+# --------------------------------------------------------------------------
+# E0 as the running best estimate (Sec. II.A, Eq. imag_prop)
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class E0State:
+    """Reading: E0 of Eq. (imag_prop) is "the best estimate of the ground-
+    state energy".  With updates on, E0 for the next step is the mean of the
+    weighted per-step estimates E_k = sum W Ebar / sum W (Sec. II.A) over the
+    last `window` steps that had weight; a step with sum W = 0 leaves E0 as
+    it is.  e0 holds the current value."""
+    e0: float
+    window: int = 10
+    recent: list = dataclasses.field(default_factory=list)
+
+
+def update_e0(state: E0State, estimator) -> float:
+    """Feed one step's (sum W Ebar, sum W); returns the E0 of the next step."""
+    num, den = estimator
+    if den > 0.0 and math.isfinite(num / den):
+        state.recent.append(num / den)
+        if len(state.recent) > state.window:
+            state.recent.pop(0)
+        total = 0.0
+        for e in state.recent:
+            total += e
+        state.e0 = total / len(state.recent)
+    return state.e0
+
+
+# --------------------------------------------------------------------------
+# Population control (not described in the paper)
+# --------------------------------------------------------------------------
+
+def comb_resample(weights: np.ndarray, u: float):
+    """Systematic ("comb") resampling of a walker population by weight.
+
+    Reading: the paper gives no population-control scheme; this is the
+    standard comb.  With T = sum_w W_w and the running sums
+    C_i = W_0 + ... + W_i (both added left to right), slot j of the new
+    population copies walker i(j) = min{i : C_i > (j + u) T / n}, for one
+    uniform u in [0, 1) per step.  Every copy gets weight 1 (the estimator
+    is a ratio, so the scale of the weights drops out).  Returns the list of
+    source indices, or None when T = 0 (an extinct population is left as
+    it is)."""
+    n = len(weights)
+    total = 0.0
+    csum = np.empty(n)
+    for i in range(n):
+        total += float(weights[i])
+        csum[i] = total
+    if not total > 0.0:
+        return None
+    src = []
+    i = 0
+    for j in range(n):
+        z = (j + u) * total / n
+        while i < n - 1 and not csum[i] > z:
+            i += 1
+        src.append(i)
+    return src
+
+
+def pop_control_due(step: int, every: int) -> bool:
+    """Population control after global step t when (t + 1) % every == 0."""
+    return every > 0 and (step + 1) % every == 0
 
 
 # --------------------------------------------------------------------------

@@ -27,10 +27,10 @@ EXPORTED = (
     "afq_init_walkers", "afq_propagate_batch", "afq_local_energy_batch",
     "afq_local_energy_adjoint", "afq_force_bias_adjoint", "afq_get_walkers",
     "afq_set_walkers", "afq_fill_fields", "afq_get_counters", "afq_profile",
-    "afq_profile_read", "afq_sync", "afq_autotune",
+    "afq_profile_read", "afq_sync", "afq_autotune", "afq_get_e0",
 )
 PHASES = ("fields", "force_bias", "opbuild", "onebody", "exponential", "overlap", "weight", "qr",
-          "exchange", "energy", "coulomb")
+          "exchange", "energy", "coulomb", "pop_control")
 
 
 class AfqError(RuntimeError):
@@ -54,6 +54,8 @@ class PropParams(ctypes.Structure):
         ("fields", ctypes.c_void_p),
         ("energies_out", ctypes.c_void_p),
         ("schedule", ctypes.c_int32),
+        ("e0_window", ctypes.c_int32),
+        ("pop_every", ctypes.c_int32),
     ]
 
 
@@ -78,7 +80,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "afq_get_walkers": (i32, [P, i32, P, P, P, P, ctypes.c_int]),
         "afq_set_walkers": (i32, [P, i32, P, P, ctypes.c_int]),
         "afq_fill_fields": (i32, [P, u64, u64, u64, i64, i64, P]),
-        "afq_get_counters": (i32, [P, i32, ctypes.POINTER(i64)]),
+        "afq_get_counters": (i32, [P, i32, ctypes.POINTER(i64), i32]),
+        "afq_get_e0": (i32, [P, i32, ctypes.POINTER(d)]),
         "afq_profile": (i32, [P, ctypes.c_int]),
         "afq_profile_read": (i32, [P, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]),
         "afq_sync": (i32, [P]),
@@ -181,7 +184,8 @@ class Context:
     # --------------------------------------------------------------- stepping
     def propagate_batch(self, sys_ids, *, tau, n_steps, exp_method=EXP_KRYLOV, exp_order=6,
                         reorth_every=1, precision=PREC_FP64, energy_every=1, e0=None, seed=0,
-                        step0=0, fields=None, energies_out=None, schedule=SCHED_AUTO):
+                        step0=0, fields=None, energies_out=None, schedule=SCHED_AUTO,
+                        e0_window=0, pop_every=0):
         ids = [sys_ids] if isinstance(sys_ids, int) else list(sys_ids)
         arr = (ctypes.c_int32 * len(ids))(*ids)
         fp, fdev, fk = _arg(fields, np.float64)
@@ -193,7 +197,7 @@ class Context:
         prm = PropParams(float(tau), int(exp_method), int(exp_order), int(reorth_every),
                          int(precision), int(n_steps), int(energy_every),
                          math.nan if e0 is None else float(e0), int(seed), int(step0), fp, ep,
-                         int(schedule))
+                         int(schedule), int(e0_window), int(pop_every))
         self._check(self._lib.afq_propagate_batch(self._h, arr, len(ids), ctypes.byref(prm)))
 
     def autotune(self, sys_ids, reps: int = 3, **_ignored):
@@ -242,10 +246,15 @@ class Context:
                                               out.shape[1], p))
 
     def get_counters(self, sys_id: int):
-        out = (ctypes.c_int64 * 4)()
-        self._check(self._lib.afq_get_counters(self._h, sys_id, out))
-        return {"live": out[0], "capped_f": out[1], "krylov_breakdowns": out[2],
-                "frozen": out[3]}
+        out = (ctypes.c_int64 * 5)()
+        self._check(self._lib.afq_get_counters(self._h, sys_id, out, 5))
+        return {"not_frozen": out[0], "capped_f": out[1], "krylov_breakdowns": out[2],
+                "frozen": out[3], "weighted": out[4]}
+
+    def get_e0(self, sys_id: int) -> float:
+        v = ctypes.c_double()
+        self._check(self._lib.afq_get_e0(self._h, sys_id, ctypes.byref(v)))
+        return v.value
 
     def local_energy_adjoint(self, sys_id: int, dE_dEL, grad_h, grad_L):
         a, adev, _ = _arg(dE_dEL, np.float64)

@@ -7,6 +7,17 @@
 #include <string>
 #include <vector>
 
+// E0 of a system on the device (read by the weight and energy kernels, so
+// that captured launches follow updates): the current value and a ring of
+// the last per-step estimates for the running-mean update.
+constexpr int kE0Max = 64;
+constexpr int kCounters = 5;
+struct E0Dev {
+  double e0;
+  int count, head;
+  double ring[kE0Max];
+};
+
 // Device arrays of one system.  Complex walker data are planar (separate
 // real and imaginary arrays); a walker's orbitals are stored orbital-major,
 // [w][j][p], so that one orbital is a contiguous M-vector.
@@ -57,7 +68,24 @@ struct SysDev {
   int* kdim = nullptr;        // [W][N]
   double* oinv = nullptr;     // [W][N][N][2]
   double* est = nullptr;      // [2] estimator scratch
-  int* counters = nullptr;    // [4] device counters of the last propagate call
+  // device counters of the last propagate call: [0] walkers not frozen at
+  // the last measured step, [1] capped force-bias components, [2] Krylov
+  // breakdowns, [3] walkers frozen, [4] walkers with W > 0 at the last
+  // measured step
+  int* counters = nullptr;
+  E0Dev* e0s = nullptr;       // E0 and its update history
+  // generation of the walker-side buffers: bumped by every (re)allocation,
+  // part of the key of a captured step graph
+  uint64_t gen = 0;
+  // Coulomb vector and exchange terms of a measurement-only BF16-split
+  // local energy (so that it leaves the step's own arrays alone)
+  double *mell_re = nullptr, *mell_im = nullptr, *mex_re = nullptr, *mex_im = nullptr;
+  // population control scratch: running weight sums, source slots, flag,
+  // and the gathered log-overlaps / energies [W][5]
+  double* pc_cum = nullptr;
+  int* pc_src = nullptr;
+  int* pc_flag = nullptr;
+  double* pc_small = nullptr;
   // mixed precision (BF16-split) operands
   int mx_pieces = 0;          // pieces of the current split arrays (0 = none)
   int Kp = 0;                 // K (= M) padded to a multiple of 32
@@ -190,8 +218,9 @@ hipError_t launch_overlap(SysDev& s, int W, const double* ph_re, const double* p
                           double* logdet_out, double* th_re, double* th_im, int* bad,
                           hipStream_t st);
 // Weight update; qr_logr (nullable) holds the log det R of this step's QR.
-hipError_t launch_weight(SysDev& s, double tau, double e0, const double* qr_logr,
-                         hipStream_t st);
+// Weight update against the system's device E0; qr_logr (nullable) holds
+// the log det R of this step's QR.
+hipError_t launch_weight(SysDev& s, double tau, const double* qr_logr, hipStream_t st);
 // Reorthonormalisation of (ph_re, ph_im) in place; writes qr_logr[W] and
 // marks walkers whose factorisation fails in s.bad.
 // With cs set, the kernel itself decides from the device step whether this
@@ -231,11 +260,17 @@ hipError_t launch_coulomb(SysDev& s, const double* th_re, const double* th_im, d
 void exchange_candidates(int N, std::vector<int2>& out);
 hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* ell_im,
                          const double* ex_re, const double* ex_im, double* eloc, double* ecap,
-                         double e0, double tau, hipStream_t st);
-// With cs->energies set, out2 is replaced by row `row` of that array at the device step.
+                         const E0Dev* e0s, double tau, hipStream_t st);
+// With cs->energies set, out2 is replaced by row `row` of that array at the
+// device step.  e0_window > 0: E0 follows the running mean of the estimates.
 hipError_t launch_estimator(SysDev& s, double* out2, hipStream_t st, const CallState* cs = nullptr,
-                            int add = 0, int64_t row = 0);
-hipError_t launch_counters(SysDev& s, int reset, hipStream_t st);
+                            int add = 0, int64_t row = 0, int e0_window = 0);
+hipError_t launch_set_e0(SysDev& s, double e0, hipStream_t st);
+// Comb resampling of the walkers by weight after global step `step` when
+// (step + 1) % every == 0 (device step under replay when cs is set).
+hipError_t launch_pop_control(SysDev& s, uint64_t seed, uint64_t sid, uint64_t step, int every,
+                              hipStream_t st, const CallState* cs = nullptr, int add = 0);
+hipError_t launch_zero_counters(SysDev& s, hipStream_t st);
 // Boundary layout (complex128 [W][M][N], interleaved) <-> planar [W][N][M].
 hipError_t launch_to_planar(const double* in, int W, int M, int N, double* re, double* im,
                             hipStream_t st);

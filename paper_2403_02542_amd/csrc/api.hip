@@ -202,6 +202,7 @@ afq_status ensure_krylov(afq_ctx* ctx, int32_t sid, SysDev& s, int k) {
   TRY(dalloc(ctx, own, &s.kb_im, WN * k * s.M));
   TRY(dalloc(ctx, own, &s.kh, WN * k * k * 2));
   s.kmax = k;
+  ++s.gen;
   (void)sid;
   return AFQ_OK;
 }
@@ -234,6 +235,7 @@ afq_status ensure_mixed(afq_ctx* ctx, int32_t sid, SysDev& s, int pieces) {
   if (!s.thb) {
     TRY(dalloc(ctx, wown, &s.thb, (size_t)3 * s.W * 2 * s.N * s.Kp));
     s.thb_ps = (int64_t)s.W * 2 * s.N * s.Kp;
+    ++s.gen;
   }
   HIPCHK(launch_split(s.Lx, rows, s.M, s.M, s.Kp, pieces, s.Lxb_ps, s.Lxb, ctx->stream));
   s.mx_pieces = pieces;
@@ -241,10 +243,10 @@ afq_status ensure_mixed(afq_ctx* ctx, int32_t sid, SysDev& s, int pieces) {
 }
 
 // Local energy and Coulomb vector of the current walkers (Theta in th_*).
-afq_status eval_energy(afq_ctx* ctx, SysDev& s, double e0, double tau) {
+afq_status eval_energy(afq_ctx* ctx, SysDev& s) {
   HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
                          ctx->stream));
-  HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, e0, tau,
+  HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, s.e0s, 0.0,
                        ctx->stream));
   return AFQ_OK;
 }
@@ -315,11 +317,6 @@ int op_pieces_of(int prec) {
   return prec == AFQ_PREC_MIXED ? 3 : prec == AFQ_PREC_MIXED_FAST ? 2 : 0;
 }
 
-// E0 of a system for a propagate call: the call's value, or the trial energy.
-double e0_of(const SysDev& s, const afq_prop_params& P) {
-  return std::isnan(P.e0) ? s.e_trial : P.e0;
-}
-
 bool reorth_due(uint64_t t, int every) { return every > 0 && ((t + 1) % (uint64_t)every) == 0; }
 
 // Everything of one walker step up to the new Green's function: fields,
@@ -380,7 +377,7 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
   }
   {
     Phase ph(ctx, AFQ_PH_WEIGHT);
-    HIPCHK(launch_weight(s, P.tau, e0_of(s, P), qr ? s.qr_logr : nullptr, st));
+    HIPCHK(launch_weight(s, P.tau, qr ? s.qr_logr : nullptr, st));
   }
   {
     Phase ph(ctx, AFQ_PH_WEIGHT);
@@ -410,11 +407,22 @@ afq_status step_exchange(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, hipS
 afq_status step_energy(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, int si, int row,
                        const CallState* cs, int add, hipStream_t st) {
   Phase ph(ctx, AFQ_PH_ENERGY);
-  HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, e0_of(s, P),
-                       P.tau, st));
+  HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, s.e0s, P.tau,
+                       st));
   double* out = (!cs && P.energies_out) ? P.energies_out + ((size_t)row * P.n_steps + si) * 2
                                         : s.est;
-  HIPCHK(launch_estimator(s, out, st, cs, add, row));
+  HIPCHK(launch_estimator(s, out, st, cs, add, row, P.e0_window));
+  return AFQ_OK;
+}
+
+// Population control after the step (comb resampling; the kernels decide
+// from the step index whether it is due).
+afq_status step_pop(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_params& P, uint64_t t,
+                    const CallState* cs, int add, hipStream_t st) {
+  if (P.pop_every <= 0) return AFQ_OK;
+  if (!cs && (t + 1) % (uint64_t)P.pop_every != 0) return AFQ_OK;
+  Phase ph(ctx, AFQ_PH_POPCTL);
+  HIPCHK(launch_pop_control(s, P.seed, (uint64_t)sid, t, P.pop_every, st, cs, add));
   return AFQ_OK;
 }
 
@@ -433,6 +441,7 @@ afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_para
     Phase ph(ctx, AFQ_PH_COULOMB);
     HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, ctx->stream));
   }
+  TRY(step_pop(ctx, sid, s, P, t, nullptr, 0, ctx->stream));
   return AFQ_OK;
 }
 
@@ -474,6 +483,15 @@ std::vector<std::vector<int>> assign_branches(const std::vector<SysDev*>& ss, in
     load[b] += step_cost(*ss[i], k);
   }
   return br;
+}
+
+// Destroys every cached step graph (the caller has waited for the stream).
+void clear_graphs(afq_ctx* ctx) {
+  for (auto& g : ctx->graphs) {
+    (void)hipGraphExecDestroy(g.ex);
+    (void)hipGraphDestroy(g.g);
+  }
+  ctx->graphs.clear();
 }
 
 template <class T>
@@ -542,6 +560,8 @@ afq_status get_xtable(afq_ctx* ctx, const std::vector<SysDev*>& ss, afq_ctx::XTa
   }
   if (ctx->xtables.size() >= 16) {   // bound the cache; tables in use are waited for
     HIPCHK(hipDeviceSynchronize());
+    // captured graphs hold pointers to these tables: they go with them
+    clear_graphs(ctx);
     for (auto& o : ctx->xtables) {
       (void)hipFree(o.d_sys);
       (void)hipFree(o.d_tiles);
@@ -579,7 +599,10 @@ afq_status batch_step(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev
   } else {
     for (SysDev* s : ss) TRY(step_exchange(ctx, *s, P, origin));
   }
-  for (int i = 0; i < (int)ss.size(); ++i) TRY(step_energy(ctx, *ss[i], P, si, i, cs, add, origin));
+  for (int i = 0; i < (int)ss.size(); ++i) {
+    TRY(step_energy(ctx, *ss[i], P, si, i, cs, add, origin));
+    TRY(step_pop(ctx, ids[i], *ss[i], P, t, cs, add, origin));
+  }
   return AFQ_OK;
 }
 
@@ -590,13 +613,19 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
   const int n = (int)ss.size();
   std::vector<char> key;
   for (int i = 0; i < n; ++i) {
+    // the buffer generation changes with every (re)allocation of the
+    // system's walker-side arrays, so a graph never outlives its buffers
+    const SysDev& s = *ss[i];
     put_bytes(key, ids[i]);
-    put_bytes(key, ss[i]->th_re);
-    put_bytes(key, ss[i]->phi_re);
-    put_bytes(key, e0_of(*ss[i], P));
-    put_bytes(key, ss[i]->x_ga);
-    put_bytes(key, ss[i]->x_wb);
-    put_bytes(key, ss[i]->mv_ct);
+    put_bytes(key, s.gen);
+    put_bytes(key, s.W);
+    put_bytes(key, s.N);
+    put_bytes(key, s.M);
+    put_bytes(key, s.th_re);
+    put_bytes(key, s.phi_re);
+    put_bytes(key, s.x_ga);
+    put_bytes(key, s.x_wb);
+    put_bytes(key, s.mv_ct);
   }
   put_bytes(key, P.tau);
   put_bytes(key, P.exp_method);
@@ -604,6 +633,8 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
   put_bytes(key, P.reorth_every);
   put_bytes(key, P.precision);
   put_bytes(key, P.seed);
+  put_bytes(key, P.e0_window);
+  put_bytes(key, P.pop_every);
   afq_ctx::GraphEntry* ge = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) ge = &g;
@@ -648,11 +679,7 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
     }
     if (ctx->graphs.size() >= 4) {
       HIPCHK(hipStreamSynchronize(origin));
-      for (auto& o : ctx->graphs) {
-        (void)hipGraphExecDestroy(o.ex);
-        (void)hipGraphDestroy(o.g);
-      }
-      ctx->graphs.clear();
+      clear_graphs(ctx);
     }
     ctx->graphs.push_back(std::move(g));
     ge = &ctx->graphs.back();
@@ -716,10 +743,7 @@ void afq_destroy(afq_ctx* ctx) {
     (void)hipEventDestroy(e.b);
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  for (auto& g : ctx->graphs) {
-    (void)hipGraphExecDestroy(g.ex);
-    (void)hipGraphDestroy(g.g);
-  }
+  clear_graphs(ctx);
   for (auto& t : ctx->xtables) {
     (void)hipFree(t.d_sys);
     (void)hipFree(t.d_tiles);
@@ -872,7 +896,7 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
   std::vector<double> zeros((size_t)N * M, 0.0);
   if (e == hipSuccess) e = hipMemcpy(tim, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_exchange(s, 1, tre, tim, lr, li, xr, xi, ctx->stream);
-  if (e == hipSuccess) e = launch_energy(s, 1, lr, li, xr, xi, el, nullptr, 0.0, 0.0, ctx->stream);
+  if (e == hipSuccess) e = launch_energy(s, 1, lr, li, xr, xi, el, nullptr, nullptr, 0.0, ctx->stream);
   double eh[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(eh, el, 16, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -894,7 +918,11 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   if (n_walkers < 1 || n_walkers > (1 << 20)) return fail(ctx, AFQ_EINVAL, "n_walkers out of range");
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  // cached graphs may hold this system's buffers, which are freed here
+  clear_graphs(ctx);
   free_all(s.walker_allocs);
+  ++s.gen;
+  s.mell_re = s.mell_im = s.mex_re = s.mex_im = nullptr;
   s.kmax = 0;
   s.kb_re = s.kb_im = s.kh = nullptr;
   s.thb = nullptr;
@@ -932,8 +960,14 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   TRY(dalloc(ctx, own, &s.kbeta, W * s.N));
   TRY(dalloc(ctx, own, &s.kdim, W * s.N));
   TRY(dalloc(ctx, own, &s.est, 2));
-  TRY(dalloc(ctx, own, &s.counters, 4));
-  HIPCHK(hipMemsetAsync(s.counters, 0, 4 * sizeof(int), ctx->stream));
+  TRY(dalloc(ctx, own, &s.counters, kCounters));
+  TRY(dalloc(ctx, own, &s.e0s, 1));
+  TRY(dalloc(ctx, own, &s.pc_cum, W));
+  TRY(dalloc(ctx, own, &s.pc_src, W));
+  TRY(dalloc(ctx, own, &s.pc_flag, 1));
+  TRY(dalloc(ctx, own, &s.pc_small, W * 5));
+  HIPCHK(launch_zero_counters(s, ctx->stream));
+  HIPCHK(launch_set_e0(s, s.e_trial, ctx->stream));
   if (phi0) {
     const double* src = (const double*)phi0;
     std::vector<void*> tmp;
@@ -960,7 +994,7 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   hipLaunchKernelGGL(k_init_alive, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, ctx->stream,
                      s.W, s.bad, s.alive, s.weight, 1);
   HIPCHK(hipGetLastError());
-  TRY(eval_energy(ctx, s, 0.0, 0.0));
+  TRY(eval_energy(ctx, s));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return AFQ_OK;
 } catch (...) {
@@ -979,6 +1013,9 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     return fail(ctx, AFQ_EINVAL, "unknown precision");
   if (P->n_steps < 0) return fail(ctx, AFQ_EINVAL, "n_steps < 0");
   if (P->fields && n_sys != 1) return fail(ctx, AFQ_EINVAL, "explicit fields need a single system");
+  if (P->e0_window < 0 || P->e0_window > kE0Max)
+    return fail(ctx, AFQ_EINVAL, "e0_window must be in [0, 64]");
+  if (P->pop_every < 0) return fail(ctx, AFQ_EINVAL, "pop_every < 0");
   if (P->schedule < AFQ_SCHED_AUTO || P->schedule > AFQ_SCHED_GRAPH)
     return fail(ctx, AFQ_EINVAL, "unknown schedule");
   const bool batch_ok = !P->fields && P->energy_every <= 1 && !ctx->profiling;
@@ -1020,6 +1057,7 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
         HIPCHK(hipMemsetAsync(s.Ab, 0, sizeof(unsigned short) * 3 * s.Ab_ps, ctx->stream));
         s.avb_ps = (int64_t)2 * s.W * s.Gp;
         TRY(dalloc(ctx, s.walker_allocs, &s.avb, (size_t)3 * s.avb_ps));
+        ++s.gen;
       }
       if (!s.Ltb) {
         s.Ltb_ps = (int64_t)s.M * s.M * s.Gp;
@@ -1031,8 +1069,10 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
       SysDev& s = *ss[i];
       const size_t n = (size_t)coulomb_slices(s.W, s.G, s.N * s.M) * s.W * s.G;
       TRY(dalloc(ctx, s.walker_allocs, &s.coul_ws, n));
+      ++s.gen;
     }
-    HIPCHK(hipMemsetAsync(ss[i]->counters, 0, 4 * sizeof(int), ctx->stream));
+    HIPCHK(launch_zero_counters(*ss[i], ctx->stream));
+    if (!std::isnan(P->e0)) HIPCHK(launch_set_e0(*ss[i], P->e0, ctx->stream));
   }
   if (mode == AFQ_SCHED_SERIAL) {
     for (int si = 0; si < P->n_steps; ++si)
@@ -1150,15 +1190,24 @@ afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precisio
     return fail(ctx, AFQ_EINVAL, "unknown precision");
   HIPCHK(hipSetDevice(ctx->device));
   if (energy_pieces(precision) == 0) {
-    TRY(eval_energy(ctx, s, 0.0, 0.0));
+    TRY(eval_energy(ctx, s));
   } else {
     TRY(ensure_mixed(ctx, sys_id, s, energy_pieces(precision)));
+    // a measurement must not change the next step: the BF16-split Coulomb
+    // vector goes to scratch, the force bias keeps reading the step's own
+    if (!s.mell_re) {
+      const size_t n = (size_t)s.W * (s.G + 1);
+      TRY(dalloc(ctx, s.walker_allocs, &s.mell_re, n));
+      TRY(dalloc(ctx, s.walker_allocs, &s.mell_im, n));
+      TRY(dalloc(ctx, s.walker_allocs, &s.mex_re, n));
+      TRY(dalloc(ctx, s.walker_allocs, &s.mex_im, n));
+    }
     HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps, s.thb,
                               ctx->stream));
-    HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
+    HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.mell_re, s.mell_im, s.mex_re, s.mex_im,
                               ctx->stream));
-    HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, 0.0, 0.0,
-                         ctx->stream));
+    HIPCHK(launch_energy(s, s.W, s.mell_re, s.mell_im, s.mex_re, s.mex_im, s.eloc, nullptr,
+                         nullptr, 0.0, ctx->stream));
   }
   TRY(copy_out(ctx, eloc_out, s.eloc, (size_t)s.W * 16, ptr_is_device));
   if (ell_out) {
@@ -1166,7 +1215,9 @@ afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precisio
     double* d = nullptr;
     if (!ptr_is_device) TRY(dalloc(ctx, tmp, &d, (size_t)s.W * s.G * 2));
     double* dst = ptr_is_device ? ell_out : d;
-    hipError_t e = launch_pack_complex(s.ell_re, s.ell_im, s.W, s.G + 1, s.G, dst, ctx->stream);
+    const bool mx = energy_pieces(precision) != 0;
+    hipError_t e = launch_pack_complex(mx ? s.mell_re : s.ell_re, mx ? s.mell_im : s.ell_im, s.W,
+                                       s.G + 1, s.G, dst, ctx->stream);
     afq_status r = AFQ_OK;
     if (e != hipSuccess) r = fail(ctx, AFQ_EDEVICE, hipGetErrorString(e));
     if (r == AFQ_OK && !ptr_is_device) r = copy_out(ctx, ell_out, d, (size_t)s.W * s.G * 16, 0);
@@ -1237,7 +1288,7 @@ afq_status afq_set_walkers(afq_ctx* ctx, int32_t sys_id, const void* phi, const 
   hipLaunchKernelGGL(k_init_alive, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, ctx->stream,
                      s.W, s.bad, s.alive, s.weight, 0);
   HIPCHK(hipGetLastError());
-  TRY(eval_energy(ctx, s, 0.0, 0.0));
+  TRY(eval_energy(ctx, s));
   return AFQ_OK;
 } catch (...) {
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
@@ -1252,16 +1303,28 @@ afq_status afq_fill_fields(afq_ctx* ctx, uint64_t seed, uint64_t sys_id, uint64_
   return AFQ_OK;
 }
 
-afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out4) {
+afq_status afq_get_counters(afq_ctx* ctx, int32_t sys_id, int64_t* out, int32_t n) {
   SysDev* sp;
   TRY(get_sys(ctx, sys_id, &sp));
-  if (!out4) return fail(ctx, AFQ_EINVAL, "null out4");
+  if (!out) return fail(ctx, AFQ_EINVAL, "null out");
+  if (n < 1 || n > kCounters) return fail(ctx, AFQ_EINVAL, "n must be in [1, 5]");
   if (!sp->W) return fail(ctx, AFQ_ESTATE, "no walkers");
   HIPCHK(hipSetDevice(ctx->device));
-  int h[4];
+  int h[kCounters];
   HIPCHK(hipMemcpyAsync(h, sp->counters, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < 4; ++i) out4[i] = h[i];
+  for (int i = 0; i < n; ++i) out[i] = h[i];
+  return AFQ_OK;
+}
+
+afq_status afq_get_e0(afq_ctx* ctx, int32_t sys_id, double* e0_out) {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  if (!e0_out) return fail(ctx, AFQ_EINVAL, "null e0_out");
+  if (!sp->W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipMemcpyAsync(e0_out, &sp->e0s->e0, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return AFQ_OK;
 }
 

@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void k_overlap(int N, int M, const double* __r
 // dtheta = Im log R;  m = exp(-tau (Re E_H - E0)), m >= 10 -> 0;
 // W <- W m max(0, cos dtheta).  A walker whose new state is non-finite is
 // frozen (alive = 0, W = 0); frozen walkers are never updated again.
-__global__ void k_weight(int W, double tau, double e0, double e_const,
+__global__ void k_weight(int W, double tau, const E0Dev* __restrict__ e0s, double e_const,
                          const double* __restrict__ logdet_n, double* __restrict__ logdet,
                          const double* __restrict__ scal, const int* __restrict__ bad,
                          const double* __restrict__ qr_logr, int* __restrict__ alive,
@@ -377,6 +377,7 @@ __global__ void k_weight(int W, double tau, double e0, double e_const,
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
   if (!alive[w]) return;
+  const double e0 = e0s->e0;
   if (bad[w]) {
     alive[w] = 0;
     weight[w] = 0.0;
@@ -551,8 +552,8 @@ __global__ __launch_bounds__(256) void k_energy(int G, int G1, double e_core,
                                                 const double* __restrict__ ex_re,
                                                 const double* __restrict__ ex_im,
                                                 double* __restrict__ eloc,
-                                                double* __restrict__ ecap, double e0,
-                                                double dE) {
+                                                double* __restrict__ ecap,
+                                                const E0Dev* __restrict__ e0s, double dE) {
   __shared__ double red[4];
   const int w = blockIdx.x;
   const double* lr = ell_re + (int64_t)w * G1;
@@ -573,6 +574,7 @@ __global__ __launch_bounds__(256) void k_energy(int G, int G1, double e_core,
     if (ecap) {
       double c = er;
       if (dE > 0.0) {
+        const double e0 = e0s->e0;
         if (!(c >= e0 - dE)) c = e0 - dE;   // NaN goes to the lower edge
         if (c > e0 + dE) c = e0 + dE;
       }
@@ -581,31 +583,177 @@ __global__ __launch_bounds__(256) void k_energy(int G, int G1, double e_core,
   }
 }
 
-// (sum_w W_w Ebar_w, sum_w W_w) over live walkers, fixed order.
+// (sum_w W_w Ebar_w, sum_w W_w) over live walkers, fixed order.  counts[0]:
+// walkers not frozen, counts[4]: walkers with W > 0.  With window > 0, E0
+// for the next step becomes the mean of the last `window` per-step estimates
+// with sum W > 0 (oldest first), the running best estimate of Sec. II.A.
 __global__ __launch_bounds__(256) void k_estimator(int W, const double* __restrict__ weight,
                                                    const double* __restrict__ ecap,
                                                    const int* __restrict__ alive,
-                                                   double* __restrict__ out2, int* __restrict__ nlive,
+                                                   double* __restrict__ out2, int* __restrict__ counts,
                                                    const CallState* __restrict__ cs, int add,
-                                                   int64_t row) {
+                                                   int64_t row, E0Dev* __restrict__ e0s,
+                                                   int window) {
   __shared__ double red[4];
   if (cs && cs->energies)
     out2 = cs->energies + (row * cs->n_steps + (int64_t)(cs->step + (uint64_t)add - cs->step0)) * 2;
-  double a = 0.0, b = 0.0, c = 0.0;
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
   for (int w = threadIdx.x; w < W; w += 256) {
     if (alive[w]) {
       a += weight[w] * ecap[w];
       b += weight[w];
       c += 1.0;
+      d += weight[w] > 0.0 ? 1.0 : 0.0;
     }
   }
   a = block_sum(a, red);
   b = block_sum(b, red);
   c = block_sum(c, red);
+  d = block_sum(d, red);
   if (threadIdx.x == 0) {
     out2[0] = a;
     out2[1] = b;
-    if (nlive) *nlive = (int)c;
+    if (counts) {
+      counts[0] = (int)c;
+      counts[4] = (int)d;
+    }
+    if (window > 0 && b > 0.0) {
+      const double e = a / b;
+      if (isfinite(e)) {
+        const int win = window < kE0Max ? window : kE0Max;
+        e0s->ring[e0s->head] = e;
+        e0s->head = (e0s->head + 1) % win;
+        if (e0s->count < win) ++e0s->count;
+        double tot = 0.0;
+        for (int i = 0; i < e0s->count; ++i)
+          tot += e0s->ring[(e0s->head - e0s->count + i + win) % win];
+        e0s->e0 = tot / e0s->count;
+      }
+    }
+  }
+}
+
+__global__ void k_zero_counters(int* c) {
+  if (threadIdx.x < kCounters) c[threadIdx.x] = 0;
+}
+
+__global__ void k_set_e0(E0Dev* e0s, double e0) {
+  e0s->e0 = e0;
+  e0s->count = 0;
+  e0s->head = 0;
+}
+
+// ---------------------------------------------------------------- population control
+// Comb resampling (not described in the paper): with T = sum_w W_w and the
+// running sums C_i (both added left to right by one thread), slot j copies
+// walker src[j] = min{i : C_i > (j + u) T / n}, u from Philox4x64-10 under
+// the key (seed, sid + 2^32), counter step + 1, word 0.  Due after global step
+// t when (t + 1) % every == 0 (read from the device step under replay);
+// T = 0 leaves the population alone.  flag[0] = 1 when the copies run.
+__global__ __launch_bounds__(256) void k_comb_select(int W, const double* __restrict__ weight,
+                                                     uint64_t seed, uint64_t sid, uint64_t step,
+                                                     const CallState* __restrict__ cs, int add,
+                                                     int every, double* __restrict__ csum,
+                                                     int* __restrict__ src, int* __restrict__ flag) {
+  __shared__ double tot_s;
+  if (cs) step = cs->step + (uint64_t)add;
+  const bool due = every > 0 && (step + 1) % (uint64_t)every == 0;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    if (due)
+      for (int i = 0; i < W; ++i) {
+        t += weight[i];
+        csum[i] = t;
+      }
+    tot_s = t;
+    flag[0] = due && t > 0.0 ? 1 : 0;
+  }
+  __syncthreads();
+  const double T = tot_s;
+  if (!(due && T > 0.0)) return;
+  U64x4 c;
+  c.v[0] = step + 1;
+  c.v[1] = c.v[2] = c.v[3] = 0;
+  const U64x4 r = philox4x64_10(c, seed, sid + (1ull << 32));
+  const double u = (double)(r.v[0] >> 11) * 0x1.0p-53;
+  for (int j = threadIdx.x; j < W; j += blockDim.x) {
+    const double z = ((double)j + u) * T / (double)W;
+    int lo = 0, hi = W - 1;   // first i with csum[i] > z (the last if none)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (csum[mid] > z) hi = mid;
+      else lo = mid + 1;
+    }
+    src[j] = lo;
+  }
+}
+
+// dst[j] = src-walker copy of every per-walker array (orbital planes NM,
+// Coulomb vector G1, log-overlap 2, energies 3).
+__global__ void k_comb_gather(int NM, int G1, const int* __restrict__ flag, const int* __restrict__ src,
+                              const double* __restrict__ ph_re, const double* __restrict__ ph_im,
+                              const double* __restrict__ th_re, const double* __restrict__ th_im,
+                              const double* __restrict__ ell_re, const double* __restrict__ ell_im,
+                              const double* __restrict__ logdet, const double* __restrict__ eloc,
+                              const double* __restrict__ ecap, double* __restrict__ dph_re,
+                              double* __restrict__ dph_im, double* __restrict__ dth_re,
+                              double* __restrict__ dth_im, double* __restrict__ dell_re,
+                              double* __restrict__ dell_im, double* __restrict__ small) {
+  if (!flag[0]) return;
+  const int j = blockIdx.x;
+  const int i = src[j];
+  const int64_t o = (int64_t)i * NM, d = (int64_t)j * NM;
+  for (int e = threadIdx.x; e < NM; e += blockDim.x) {
+    dph_re[d + e] = ph_re[o + e];
+    dph_im[d + e] = ph_im[o + e];
+    dth_re[d + e] = th_re[o + e];
+    dth_im[d + e] = th_im[o + e];
+  }
+  for (int e = threadIdx.x; e < G1; e += blockDim.x) {
+    dell_re[(int64_t)j * G1 + e] = ell_re[(int64_t)i * G1 + e];
+    dell_im[(int64_t)j * G1 + e] = ell_im[(int64_t)i * G1 + e];
+  }
+  if (threadIdx.x == 0) {
+    small[j * 5 + 0] = logdet[i * 2];
+    small[j * 5 + 1] = logdet[i * 2 + 1];
+    small[j * 5 + 2] = eloc[i * 2];
+    small[j * 5 + 3] = eloc[i * 2 + 1];
+    small[j * 5 + 4] = ecap[i];
+  }
+}
+
+// The gathered copies back into the walker store, weights 1.
+__global__ void k_comb_commit(int NM, int G1, const int* __restrict__ flag,
+                              const double* __restrict__ dph_re, const double* __restrict__ dph_im,
+                              const double* __restrict__ dth_re, const double* __restrict__ dth_im,
+                              const double* __restrict__ dell_re, const double* __restrict__ dell_im,
+                              const double* __restrict__ small, double* __restrict__ ph_re,
+                              double* __restrict__ ph_im, double* __restrict__ th_re,
+                              double* __restrict__ th_im, double* __restrict__ ell_re,
+                              double* __restrict__ ell_im, double* __restrict__ logdet,
+                              double* __restrict__ eloc, double* __restrict__ ecap,
+                              double* __restrict__ weight, int* __restrict__ alive) {
+  if (!flag[0]) return;
+  const int j = blockIdx.x;
+  const int64_t d = (int64_t)j * NM;
+  for (int e = threadIdx.x; e < NM; e += blockDim.x) {
+    ph_re[d + e] = dph_re[d + e];
+    ph_im[d + e] = dph_im[d + e];
+    th_re[d + e] = dth_re[d + e];
+    th_im[d + e] = dth_im[d + e];
+  }
+  for (int e = threadIdx.x; e < G1; e += blockDim.x) {
+    ell_re[(int64_t)j * G1 + e] = dell_re[(int64_t)j * G1 + e];
+    ell_im[(int64_t)j * G1 + e] = dell_im[(int64_t)j * G1 + e];
+  }
+  if (threadIdx.x == 0) {
+    logdet[j * 2] = small[j * 5 + 0];
+    logdet[j * 2 + 1] = small[j * 5 + 1];
+    eloc[j * 2] = small[j * 5 + 2];
+    eloc[j * 2 + 1] = small[j * 5 + 3];
+    ecap[j] = small[j * 5 + 4];
+    weight[j] = 1.0;
+    alive[j] = 1;
   }
 }
 
@@ -732,9 +880,8 @@ hipError_t launch_overlap(SysDev& s, int W, const double* ph_re, const double* p
   return hipGetLastError();
 }
 
-hipError_t launch_weight(SysDev& s, double tau, double e0, const double* qr_logr,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_weight, dim3(nblk(s.W, 256)), dim3(256), 0, st, s.W, tau, e0, s.e_const,
+hipError_t launch_weight(SysDev& s, double tau, const double* qr_logr, hipStream_t st) {
+  hipLaunchKernelGGL(k_weight, dim3(nblk(s.W, 256)), dim3(256), 0, st, s.W, tau, s.e0s, s.e_const,
                      s.logdet_n, s.logdet, s.scal, s.bad, qr_logr, s.alive, s.weight,
                      s.counters ? s.counters + 3 : nullptr);
   return hipGetLastError();
@@ -760,21 +907,51 @@ hipError_t launch_commit(SysDev& s, hipStream_t st) {
 
 hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* ell_im,
                          const double* ex_re, const double* ex_im, double* eloc, double* ecap,
-                         double e0, double tau, hipStream_t st) {
+                         const E0Dev* e0s, double tau, hipStream_t st) {
   double dE = 0.0;
   if (tau > 0.0) {
     const double ne = 2.0 * s.N;
     dE = 0.5 * sqrt(ne / tau) + sqrt(ne * tau);
   }
   hipLaunchKernelGGL(k_energy, dim3(W), dim3(256), 0, st, s.G, s.G + 1, s.e_core, ell_re, ell_im,
-                     ex_re, ex_im, eloc, ecap, e0, dE);
+                     ex_re, ex_im, eloc, ecap, e0s, dE);
   return hipGetLastError();
 }
 
 hipError_t launch_estimator(SysDev& s, double* out2, hipStream_t st, const CallState* cs, int add,
-                            int64_t row) {
+                            int64_t row, int e0_window) {
   hipLaunchKernelGGL(k_estimator, dim3(1), dim3(256), 0, st, s.W, s.weight, s.ecap, s.alive, out2,
-                     s.counters ? s.counters + 0 : nullptr, cs, add, row);
+                     s.counters, cs, add, row, s.e0s, e0_window);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(SysDev& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, s.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_e0(SysDev& s, double e0, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_e0, dim3(1), dim3(1), 0, st, s.e0s, e0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pop_control(SysDev& s, uint64_t seed, uint64_t sid, uint64_t step, int every,
+                              hipStream_t st, const CallState* cs, int add) {
+  const int NM = s.N * s.M, G1 = s.G + 1;
+  hipLaunchKernelGGL(k_comb_select, dim3(1), dim3(256), 0, st, s.W, s.weight, seed, sid, step, cs,
+                     add, every, s.pc_cum, s.pc_src, s.pc_flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the next-step buffers (phn, thn) and the exchange-term arrays are free
+  // between steps: they stage the copies
+  hipLaunchKernelGGL(k_comb_gather, dim3(s.W), dim3(256), 0, st, NM, G1, s.pc_flag, s.pc_src,
+                     s.phi_re, s.phi_im, s.th_re, s.th_im, s.ell_re, s.ell_im, s.logdet, s.eloc,
+                     s.ecap, s.phn_re, s.phn_im, s.thn_re, s.thn_im, s.ex_re, s.ex_im, s.pc_small);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_comb_commit, dim3(s.W), dim3(256), 0, st, NM, G1, s.pc_flag, s.phn_re,
+                     s.phn_im, s.thn_re, s.thn_im, s.ex_re, s.ex_im, s.pc_small, s.phi_re, s.phi_im,
+                     s.th_re, s.th_im, s.ell_re, s.ell_im, s.logdet, s.eloc, s.ecap, s.weight,
+                     s.alive);
   return hipGetLastError();
 }
 

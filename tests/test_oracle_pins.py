@@ -590,3 +590,64 @@ def test_p15_coulomb_vector_gradient_fd():
         dL = np.zeros((G, M, M)); dL[g, a, b] = eps
         fd = (obj(L + dL) - obj(L - dL)) / (2 * eps)
         assert fd == pytest.approx(gL[g, a, b], abs=1e-8)
+
+
+# ---------------------------------------------------------------- population layer
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_comb_resample_definition_and_unbiasedness(seed):
+    """comb_resample: slot j copies the first walker whose running weight
+    sum exceeds (j + u) T / n (numpy searchsorted on cumsum); each walker
+    is copied floor or ceil of n W_i / T times; zero weights never; and
+    over u the mean copy count is exactly n W_i / T (the comb is unbiased)."""
+    rng = np.random.default_rng(seed)
+    n = 12
+    w = rng.exponential(size=n)
+    w[[2, 7]] = 0.0
+    T = w.sum()
+    for u in (0.0, 0.37, 0.999):
+        src = O.comb_resample(w, u)
+        ref = np.searchsorted(np.cumsum(w), (np.arange(n) + u) * T / n, side="right")
+        assert list(ref) == src
+        cnt = np.bincount(src, minlength=n)
+        assert cnt[2] == 0 and cnt[7] == 0
+        assert np.all(cnt >= np.floor(n * w / T) - 1e-12) and np.all(cnt <= np.ceil(n * w / T) + 1e-12)
+    us = (np.arange(4000) + 0.5) / 4000
+    mean = np.mean([np.bincount(O.comb_resample(w, u), minlength=n) for u in us], axis=0)
+    assert np.abs(mean - n * w / T).max() < 2e-3
+    assert O.comb_resample(np.zeros(4), 0.5) is None
+
+
+def test_e0_update_running_mean():
+    """update_e0: E0 of the next step is the mean of the weighted step
+    estimates over the last `window` steps with weight; sum W = 0 keeps E0."""
+    st = O.E0State(-1.0, window=3)
+    seq = [(-2.0, 1.0), (-9.0, 3.0), (0.0, 0.0), (-8.0, 2.0), (-10.0, 2.0)]
+    got = [O.update_e0(st, e) for e in seq]
+    assert got == [pytest.approx(-2.0), pytest.approx(-2.5), pytest.approx(-2.5),
+                   pytest.approx((-2 - 3 - 4) / 3), pytest.approx((-3 - 4 - 5) / 3)]
+
+
+def test_run_population_control_copies_walkers():
+    """run with pop_every = 1: after each step the walkers are the comb's
+    copies of the pre-control walkers, with weight 1; with e0_state, p.e0 of
+    the next step is the running mean of the estimates."""
+    M, N, G = 8, 3, 5
+    h, L = _rand_system(M, G, 23, scale=0.15)
+    psi = _trial(M, N, 23)
+    p = O.prepare(h, L, 0.0, psi, 0.1)
+    rng = np.random.default_rng(4)
+    xs = rng.normal(size=(3, 6, G))
+    wks = [O.init_walker(p) for _ in range(6)]
+    st = O.E0State(p.e0, window=2)
+    us = [0.3, 0.8, 0.1]
+    pre, _ = O.run(p, wks, lambda t: xs[t], 1, O.EXP_KRYLOV, 4, 1)
+    p2 = O.prepare(h, L, 0.0, psi, 0.1)
+    post, hist = O.run(p2, wks, lambda t: xs[t], 1, O.EXP_KRYLOV, 4, 1, e0_state=st,
+                       pop_every=1, comb_u=lambda t: us[t])
+    src = hist[0]["comb"]
+    assert src == O.comb_resample(np.array([wk.weight for wk in pre]), us[0])
+    for j, i in enumerate(src):
+        assert np.array_equal(post[j].phi, pre[i].phi) and post[j].weight == 1.0
+    est = hist[0]["estimator"]
+    assert p2.e0 == pytest.approx(est[0] / est[1])

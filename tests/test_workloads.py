@@ -95,3 +95,13 @@ def test_uneven_batch_sizes():
     sizes = W.uneven_batch_sizes()
     assert len(sizes) == 48
     assert all(40 <= M <= 400 and N == M // 6 and G == 5 * M for M, N, G in sizes)
+
+
+def test_comb_uniform_follows_definition():
+    """Population-control uniforms: word 0 of the Philox block of counter
+    step + 1 under the key (seed, sys_id + 2^32), u = (x >> 11) 2^-53."""
+    for seed, sid, step in ((0, 0, 0), (0, 0, 1), (3, 2, 7), (5, 47, 123456)):
+        blk = philox4x64_10((step + 1, 0, 0, 0), (seed, sid + (1 << 32)))
+        u = (blk[0] >> 11) * 2.0 ** -53
+        assert W.comb_uniform(seed, sid, step) == u
+        assert 0.0 <= u < 1.0
