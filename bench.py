@@ -366,6 +366,27 @@ def _oracle_worker(args):
         return time.perf_counter() - t0
 
 
+def cpu_model():
+    """Host CPU model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def population_rows(est):
+    """Per-step (sum W E_L, sum W) rows as the weighted estimate E_k of
+    Sec. II.A, or "extinct" when no walker carries weight."""
+    out = []
+    for num, den in est:
+        out.append({"sum_w": float(den),
+                    "e_k": float(num / den) if den > 0 else "extinct"})
+    return out
+
+
 def cpu_baseline(cfg, ham, psi, n_procs, n_steps):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     walkers are independent, so n_procs processes (one BLAS thread each, the
@@ -383,10 +404,13 @@ def cpu_baseline(cfg, ham, psi, n_procs, n_steps):
         times = pool.map(_oracle_worker, [(w, n_steps) for w in range(n_procs)])
     wall = time.perf_counter() - t0
     rate = sum(n_steps / t for t in times)
+    per = sum(times) / (n_procs * n_steps)
     return {"value": rate, "unit": "walker-steps/s", "cores": int(n_procs), "kind": "oracle",
-            "sample": f"{n_procs} walkers (one process and one BLAS thread each) x {n_steps} "
-                      f"steps after one warm-up step, same workload and fields; "
-                      f"per-walker step time {sum(times) / (n_procs * n_steps):.3f} s, "
+            "one_thread_value": 1.0 / per, "cpu_model": cpu_model(),
+            "host_cpus_visible": len(os.sched_getaffinity(0)),
+            "sample": f"{n_procs} walkers (one process and one BLAS thread each; {n_procs} is "
+                      f"the host CPU share of one GPU) x {n_steps} steps after one warm-up step, "
+                      f"same workload and fields; per-walker step time {per:.3f} s on one thread, "
                       f"wall {wall:.1f} s"}
 
 
@@ -407,7 +431,7 @@ def main():
                     help="with --precision fp64: skip the mixed-precision runs beside it")
     ap.add_argument("--cpu-procs", type=int, default=None,
                     help="oracle processes for the CPU baseline (default: host cores, <= 16)")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates the "
                          "HBM byte counters of a profiler) and exit")
@@ -511,10 +535,14 @@ def main():
                 "roofline": roof,
                 "phases": {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]}
                            for k, v in prof.items()},
-                "energy_last_step": float(est[-1, 0] / est[-1, 1]) if est[-1, 1] else float("nan")}
+                "population": population_rows(est),
+                "first_step": step0 - args.steps}
 
     main_run = run_mode(args.precision)
     cnt = ctx.get_counters(sid)
+    if cnt["weighted"] == 0:
+        log("the walker population is extinct at the last timed step (no walker carries weight; "
+            "every walker is still propagated, so the timing covers the full step)")
     others = {}
     sparse = {}
     if args.precision == "fp64" and not args.no_mixed:
@@ -560,7 +588,13 @@ def main():
         "roofline": main_run["roofline"],
         "phases": main_run["phases"],
         "counters": cnt,
-        "energy_last_step": main_run["energy_last_step"],
+        "population": {"timed_steps_from": main_run["first_step"],
+                       "per_step": main_run["population"],
+                       "weighted_walkers_last_step": cnt["weighted"],
+                       "note": "fixed E0 = trial energy, no population control: on this "
+                               "synthetic workload the walkers lose their overlap with the "
+                               "trial within ~10 steps and the phaseless rule / reweighting "
+                               "cap zero their weights; dead walkers keep being propagated"},
         "mixed": others,
         "energy_every_10": sparse,
         "cpu_baseline": cpu,

@@ -10,11 +10,12 @@ E0, so each runs in its own process.
 
     python tests/population_report.py c2 --walkers 16 --steps 50
     python tests/population_report.py c3 --walkers 4 --steps 10
-    python tests/population_report.py c2 --e0-update --steps 50
+    python tests/population_report.py c2 --e0-update --pop-every 1 --steps 50
 
 With --e0-update, E0 follows the running weighted energy estimate (the
-update rule of `oracle.afq_oracle.update_e0`); walkers then run together
-because E0 couples them.
+update rule of `oracle.afq_oracle.update_e0`); with --pop-every r the
+population is comb-resampled after every r-th step (`comb_resample`).
+Either couples the walkers, which then run together in one process.
 """
 import argparse
 import dataclasses
@@ -81,6 +82,7 @@ def main():
     ap.add_argument("--tau", type=float, default=None)
     ap.add_argument("--procs", type=int, default=min(8, len(os.sched_getaffinity(0))))
     ap.add_argument("--e0-update", action="store_true")
+    ap.add_argument("--pop-every", type=int, default=0)
     args = ap.parse_args()
     cfg = W.CONFIGS[args.workload]
     if args.tau:
@@ -92,7 +94,7 @@ def main():
           f"QR every {cfg.reorth_every}; {args.walkers} walkers of the batch of {cfg.W}; "
           f"E_HF(trial) = E0 = {p.e0:.4f}; energy window +-{O.energy_window(2 * cfg.N, cfg.tau):.2f}; "
           f"reweighting cap at E_H < E0 - {math.log(10.0) / cfg.tau:.2f}")
-    if not args.e0_update:
+    if not args.e0_update and not args.pop_every:
         _STATE.update(cfg=cfg, p=p, n=n_steps)
         with mp.get_context("fork").Pool(args.procs) as pool:
             rows = pool.map(_walker_path, range(args.walkers))
@@ -101,17 +103,19 @@ def main():
     wks = [O.init_walker(p) for _ in range(args.walkers)]
     rows = [[] for _ in range(args.walkers)]
     e0s = []
-    state = O.E0State(p.e0)
-    for t in range(n_steps):
-        e0s.append(p.e0)
-        x = W.fields(cfg.seed, 0, t, cfg.W, cfg.G)
-        wks, hist = O.run(p, wks, lambda s: x, 1, O.EXP_KRYLOV, cfg.k, cfg.reorth_every,
-                          step0=t)
-        h = hist[0]
-        for w in range(args.walkers):
-            rows[w].append((h["weight"][w], h["e_loc"][w].real, h["e_capped"][w],
-                            h["e_hybrid"][w].real, h["zeroed_by"][w]))
-        p.e0 = O.update_e0(state, h["estimator"])
+    state = O.E0State(p.e0) if args.e0_update else None
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        for t in range(n_steps):
+            e0s.append(p.e0)
+            x = W.fields(cfg.seed, 0, t, cfg.W, cfg.G)
+            wks, hist = O.run(p, wks, lambda s: x, 1, O.EXP_KRYLOV, cfg.k, cfg.reorth_every,
+                              step0=t, e0_state=state, pop_every=args.pop_every,
+                              comb_u=lambda s: W.comb_uniform(cfg.seed, 0, s))
+            h = hist[0]
+            for w in range(args.walkers):
+                rows[w].append((h["weight"][w], h["e_loc"][w].real, h["e_capped"][w],
+                                h["e_hybrid"][w].real, h["zeroed_by"][w]))
     report(rows, e0s)
 
 
