@@ -185,6 +185,21 @@ afq_status afq_autotune(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys, int
 afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precision,
                                   double* eloc_out, double* ell_out, int ptr_is_device);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the FP64 local energy of every
+ * walker exactly as afq_local_energy_batch computes it (same kernels, same
+ * sums), with device pointers only -- eloc_out complex128 [W], ell_out
+ * complex128 [W][n_chol] or NULL -- and without any device allocation.  The
+ * per-(walker, Cholesky block) partial results live in a fixed 32 MiB
+ * workspace that the library holds on each GPU it runs on for the life of
+ * the process, so n_walkers * (n_chol + 1) must not exceed 1048576
+ * (AFQ_EINVAL otherwise).  Unlike afq_local_energy_batch the call leaves the
+ * step's own Coulomb vector alone.  Every call on a GPU shares that GPU's
+ * workspace: calls that overlap on one GPU (other contexts or streams) race;
+ * calls ordered on one stream are safe.  Enqueued on the context stream. */
+afq_status afq_local_energy_batch_noalloc(afq_ctx* ctx, int32_t sys_id, double* eloc_out,
+                                          double* ell_out);
+
 /* Adjoint of the local energy at fixed walkers and fixed Psi_T:
  * grad_h[M][M]      = sum_w dE_dEL[w] d Re E_L^w / d h,
  * grad_L[g][M][M]   = sum_w dE_dEL[w] d Re E_L^w / d L_g,

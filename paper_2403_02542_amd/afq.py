@@ -28,6 +28,7 @@ EXPORTED = (
     "afq_local_energy_adjoint", "afq_force_bias_adjoint", "afq_get_walkers",
     "afq_set_walkers", "afq_fill_fields", "afq_get_counters", "afq_profile",
     "afq_profile_read", "afq_sync", "afq_autotune", "afq_get_e0",
+    "afq_local_energy_batch_noalloc",
 )
 PHASES = ("fields", "force_bias", "opbuild", "onebody", "exponential", "overlap", "weight", "qr",
           "exchange", "energy", "coulomb", "pop_control")
@@ -82,6 +83,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "afq_fill_fields": (i32, [P, u64, u64, u64, i64, i64, P]),
         "afq_get_counters": (i32, [P, i32, ctypes.POINTER(i64), i32]),
         "afq_get_e0": (i32, [P, i32, ctypes.POINTER(d)]),
+        "afq_local_energy_batch_noalloc": (i32, [P, i32, P, P]),
         "afq_profile": (i32, [P, ctypes.c_int]),
         "afq_profile_read": (i32, [P, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]),
         "afq_sync": (i32, [P]),
@@ -220,6 +222,14 @@ class Context:
         if host:
             return (eloc_out, ell_out) if ell_out is not None else eloc_out
         return eloc_out
+
+    def local_energy_batch_noalloc(self, sys_id: int, eloc_out, ell_out=None):
+        """FP64 local energies into device tensors, with no device allocation."""
+        ep, edev, _ = _arg(eloc_out, np.complex128)
+        lp, ldev, _ = _arg(ell_out, np.complex128)
+        if not edev or (ell_out is not None and not ldev):
+            raise ValueError("the allocation-free local energy writes device tensors")
+        self._check(self._lib.afq_local_energy_batch_noalloc(self._h, sys_id, ep, lp))
 
     def get_walkers(self, sys_id: int):
         d = self.dims[sys_id]

@@ -18,6 +18,14 @@ struct PhaseEv {
   hipEvent_t a, b;
 };
 
+// Fixed device workspace of the allocation-free local energy
+// (afq_local_energy_batch_noalloc): the Coulomb vector and exchange terms of
+// every (walker, Cholesky block), four planes of W (G + 1) doubles.  Each
+// GPU holds its own copy for the life of the process; host code uses only
+// the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchDoubles = (size_t)4 << 20;   // 32 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 struct afq_ctx {
   bool profiling = false;
   std::vector<PhaseEv> pending;
@@ -51,6 +59,8 @@ struct afq_ctx {
     hipGraphExec_t ex = nullptr;
   };
   std::vector<GraphEntry> graphs;
+  // this device's address of the fixed workspace `scratch`
+  double* scratch_dev = nullptr;
 };
 
 namespace {
@@ -714,6 +724,14 @@ afq_status afq_create(afq_ctx** out, int device, void* hip_stream) {
     return AFQ_EDEVICE;
   }
   ctx->device = device;
+  // device address of the fixed workspace on this device (set-up, once per
+  // context, with the device current)
+  if (hipGetSymbolAddress((void**)&ctx->scratch_dev, HIP_SYMBOL(scratch)) != hipSuccess ||
+      !ctx->scratch_dev) {
+    (void)hipGetLastError();
+    delete ctx;
+    return AFQ_EDEVICE;
+  }
   if (hip_stream) {
     ctx->stream = (hipStream_t)hip_stream;
   } else {
@@ -1227,6 +1245,31 @@ afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precisio
   return AFQ_OK;
 } catch (...) {
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_local_energy_batch_noalloc(afq_ctx* ctx, int32_t sys_id, double* eloc_out,
+                                          double* ell_out) {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  SysDev& s = *sp;
+  if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
+  if (!eloc_out) return fail(ctx, AFQ_EINVAL, "null eloc_out");
+  const size_t n = (size_t)s.W * (s.G + 1);
+  if (4 * n > kScratchDoubles)
+    return fail(ctx, AFQ_EINVAL, "n_walkers * (n_chol + 1) = " + std::to_string(n) +
+                                     " exceeds the fixed workspace of the allocation-free local "
+                                     "energy (" + std::to_string(kScratchDoubles / 4) + ")");
+  HIPCHK(hipSetDevice(ctx->device));
+  double* lr = ctx->scratch_dev;
+  double* li = lr + n;
+  double* xr = li + n;
+  double* xi = xr + n;
+  // every element of the four planes is written by the contraction: nothing
+  // needs clearing between calls
+  HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, lr, li, xr, xi, ctx->stream));
+  HIPCHK(launch_energy(s, s.W, lr, li, xr, xi, eloc_out, nullptr, nullptr, 0.0, ctx->stream));
+  if (ell_out) HIPCHK(launch_pack_complex(lr, li, s.W, s.G + 1, s.G, ell_out, ctx->stream));
+  return AFQ_OK;
 }
 
 afq_status afq_get_walkers(afq_ctx* ctx, int32_t sys_id, void* phi, double* weight,
