@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define AFQ_DEV __device__ __forceinline__
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -68,6 +70,25 @@ AFQ_DEV double wave_sum(double v) {   // every lane of the wave must be active
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
   return __hiloint2double(hi, lo);
+}
+// wave_sum of K values at once, every step taken for all values before the
+// next (independent DPP chains interleave instead of queueing behind one
+// another); the same additions in the same order as wave_sum.  The sums are
+// complete in lane 63 only.
+template <int K>
+AFQ_DEV void wave_sum_n(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_move<0xB1, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_move<0x4E, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_move<0x141, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_move<0x140, 0xf>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_move<0x142, 0xa>(v[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_move<0x143, 0xc>(v[k]);
 }
 // Value of lane l (a compile-time constant after unrolling) in every lane,
 // through the scalar registers.
@@ -647,4 +668,162 @@ template <int WR, int WC, int RT, int CT, int PC, int BK = 16>
 constexpr size_t pipe_lds_bytes() {
   if constexpr (PC == 0) return Pipe<WR, WC, RT, CT, BK>::LDS_BYTES;
   else return PipeMx<WR, WC, RT, CT, PC>::LDS_BYTES;
+}
+
+// ---------------------------------------------------------------- exchange epilogue
+// Reduction of the T_g^w = (Psi_T^T L_g) Theta^w blocks of one local-energy
+// tile, shared by the FP64 and the BF16-split kernels.  The tile holds rows
+// (g, i) of ga Cholesky blocks and columns (w, j, plane) of wb walkers, the
+// real and imaginary parts of T_ij side by side.  The rows of `gpp`
+// consecutive Cholesky blocks (a phase) are staged in LDS in the tile's own
+// layout, Ts[row][col] with the compile-time pitch PITCH, so that every
+// accumulator element is stored at a lane base plus a constant offset.  Then
+// every block (Cholesky block, walker) of the phase is reduced to
+//   X_g = sum_ij T_ij T_ji = 2 sum_{i<j} T_ij T_ji + sum_i T_ii^2,
+//   ell_g = 2 sum_i T_ii,
+// with a fixed cut: thread t takes the pairs i < j of index
+// p = t + nthreads k (row by row) in the order of k, and thread t < N the
+// diagonal element t; wave sums, then the waves' partial sums in wave order.
+// The products are formed in MT (float64, or float32 when T itself is a
+// float32 result) and summed per thread in MT, the wave and workgroup sums in
+// float64.  The cut depends on N and the workgroup size only, so the sums do
+// not depend on the tile shape.  row_of(i, e) is the tile row of accumulator
+// element e of row tile i; the columns of tile j are j * 16 + (lane & 15).
+// The blocks of a phase are reduced up to NBMAX at a time (red holds
+// 4 NBMAX nwaves doubles).
+template <typename TS, int NB, int PITCH>
+AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, int N, double* red) {
+  typedef typename std::conditional<sizeof(TS) == 8, double2, float2>::type TS2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  const int P = N * (N - 1) / 2, twoN1 = 2 * N - 1;
+  int boff[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) boff[b] = boff_in[b];
+  TS xr[NB], xi[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) xr[b] = xi[b] = (TS)0;
+  for (int p = tid; p < P; p += nthr) {
+    // row i of pair p: C(i) = i (2N - 1 - i) / 2 pairs precede row i
+    int i = (int)(0.5f * ((float)twoN1 - sqrtf((float)(twoN1 * twoN1 - 8 * p))));
+    i = max(0, min(i, N - 2));
+    while (i > 0 && i * (twoN1 - i) / 2 > p) --i;
+    while ((i + 1) * (twoN1 - i - 1) / 2 <= p) ++i;
+    const int j = i + 1 + p - i * (twoN1 - i) / 2;
+    const int oij = i * PITCH + 2 * j, oji = j * PITCH + 2 * i;
+    TS2 a[NB], c[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      a[b] = *(const TS2*)(Ts + boff[b] + oij);
+      c[b] = *(const TS2*)(Ts + boff[b] + oji);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      xr[b] += a[b].x * c[b].x - a[b].y * c[b].y;
+      xi[b] += a[b].x * c[b].y + a[b].y * c[b].x;
+    }
+  }
+  double dr[NB], di[NB], tr[NB], ti[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) dr[b] = di[b] = tr[b] = ti[b] = 0.0;
+  if (tid < N) {
+    const int o = tid * PITCH + 2 * tid;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const TS2 d = *(const TS2*)(Ts + boff[b] + o);
+      const double x = d.x, y = d.y;
+      dr[b] = x * x - y * y;
+      di[b] = 2.0 * x * y;
+      tr[b] = x;
+      ti[b] = y;
+    }
+  }
+  double v[4 * NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    v[4 * b] = 2.0 * (double)xr[b] + dr[b];
+    v[4 * b + 1] = 2.0 * (double)xi[b] + di[b];
+    v[4 * b + 2] = tr[b];
+    v[4 * b + 3] = ti[b];
+  }
+  wave_sum_n(v);
+  if (lane == 63) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double* rr = red + (b * nwaves + wave) * 4;
+      rr[0] = v[4 * b];
+      rr[1] = v[4 * b + 1];
+      rr[2] = v[4 * b + 2];
+      rr[3] = v[4 * b + 3];
+    }
+  }
+}
+
+template <typename TS, int PITCH, int NBMAX, typename ACC, int RT, int CT, class RowOf>
+AFQ_DEV void exchange_epilogue(ACC (&acc)[RT][CT], RowOf row_of, int mtv, int N, int ga, int wb,
+                               int g0, int w0, int G1, TS* Ts, int gpp, double* red,
+                               double* __restrict__ ell_re, double* __restrict__ ell_im,
+                               double* __restrict__ ex_re, double* __restrict__ ex_im) {
+  static_assert(PITCH >= CT * 16, "pitch");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int twoN = 2 * N;
+  TS* lane_base = Ts + (lane & 15);
+  for (int gb0 = 0; gb0 < ga; gb0 += gpp) {
+    const int ngl = min(gpp, ga - gb0), nb = ngl * wb;
+    const int p0 = gb0 * N, p1 = p0 + ngl * N;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = row_of(i, e);
+        if (i < mtv && r >= p0 && r < p1) {
+          TS* d = lane_base + (r - p0) * PITCH;
+#pragma unroll
+          for (int j = 0; j < CT; ++j) d[j * 16] = (TS)acc[i][j][e];
+        }
+      }
+    __syncthreads();
+    for (int bb0 = 0; bb0 < nb; bb0 += NBMAX) {
+      const int nbb = min(NBMAX, nb - bb0);
+      int boff[NBMAX];
+#pragma unroll
+      for (int b = 0; b < NBMAX; ++b) {
+        const int bq = b < nbb ? bb0 + b : bb0;
+        const int gl = bq / wb, wl = bq - gl * wb;
+        boff[b] = gl * N * PITCH + wl * twoN;
+      }
+      // exactly nbb blocks: one instance per count
+      switch (nbb) {
+#define AFQ_REDUCE_CASE(K)                                          \
+  case K:                                                           \
+    if constexpr (K <= NBMAX) exchange_reduce<TS, K, PITCH>(Ts, boff, N, red); \
+    break;
+        AFQ_REDUCE_CASE(1)
+        AFQ_REDUCE_CASE(2)
+        AFQ_REDUCE_CASE(3)
+        AFQ_REDUCE_CASE(4)
+        AFQ_REDUCE_CASE(5)
+        AFQ_REDUCE_CASE(6)
+        AFQ_REDUCE_CASE(7)
+        AFQ_REDUCE_CASE(8)
+#undef AFQ_REDUCE_CASE
+        default: break;
+      }
+      __syncthreads();
+      if (tid < nbb) {
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < nwaves; ++w)
+          for (int k = 0; k < 4; ++k) s[k] += red[(tid * nwaves + w) * 4 + k];
+        const int gl = (bb0 + tid) / wb, wl = bb0 + tid - gl * wb;
+        const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb0 + gl;
+        ex_re[o] = s[0];
+        ex_im[o] = s[1];
+        ell_re[o] = 2.0 * s[2];
+        ell_im[o] = 2.0 * s[3];
+      }
+      __syncthreads();
+    }
+  }
 }

@@ -4,9 +4,9 @@
 // Psi_T^T h), T_g^w = (Psi_T^T L_g) Theta^w is an N x N complex matrix.
 // The kernel never stores T: a 512-thread workgroup computes the T blocks
 // of GA consecutive g-blocks and WB consecutive walkers as one MFMA tile
-//   rows (g, i): GA N,   columns (w, plane, j): WB 2N,   K = M,
-// then stages the tile in LDS a few g-blocks at a time and reduces every
-// N x N block to
+//   rows (g, i): GA N,   columns (w, j, plane): WB 2N,   K = M,
+// then stages the tile in LDS a few blocks at a time and reduces every
+// N x N block (exchange_epilogue) to
 //   ell_g = 2 tr T_g        (the mixed <Lhat_g>, also the next force bias)
 //   X_g   = tr(T_g T_g)     (exchange term)
 // The h block gives ell_G = 2 tr(Psi_T^T h Theta), the one-body energy.
@@ -80,7 +80,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
         const int c = e2 >> 4, k = k0 + (e2 & 15);
         if (c < nc && k < M) {
           const int wl = c / twoN, rem = c - wl * twoN;
-          const int pl = rem >= N, j = pl ? rem - N : rem;
+          const int pl = rem & 1, j = rem >> 1;
           const int64_t row = ((int64_t)(w0 + wl) * N + j) * M;
           v = pl ? th_im[row + k] : th_re[row + k];
         }
@@ -155,84 +155,10 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
     __syncthreads();
   }
 
-  // ---- epilogue: per walker, groups of `grp` g-blocks staged in LDS
-  double* Ts = smem;
-  double* red = smem + X_LDS - X_RED;  // partial sums [gl][wave][4]
-  const int ldt = twoN + 1;
-  const int ei0 = tid / N, ej0 = tid - ei0 * N;                  // element tid
-  const int edq = (XW * 64) / N, edr = XW * 64 - edq * N;     // advance per stride
-  for (int wl = 0; wl < wb; ++wl) {
-    for (int gb = 0; gb < ga; gb += grp) {
-      const int gn = min(grp, ga - gb);
-      const int rlo = gb * N, rhi = (gb + gn) * N;
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < X_RT; ++i) {
-        if (i >= mtv) continue;
-#pragma unroll
-        for (int j = 0; j < CT; ++j) {
-          if (j >= TC) continue;
-          const int c = j * 16 + lr - wl * twoN;
-          if (c < 0 || c >= twoN) continue;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int r = (rt0 + i) * 16 + 4 * e + lk;
-            if (r >= rlo && r < rhi) Ts[(r - rlo) * ldt + c] = acc[i][j][e];
-          }
-        }
-      }
-      __syncthreads();
-      // every g-block is cut the same way whatever the tile shape (wave w
-      // sums the elements e = w * 64 + lane (mod XW * 64) of the block), so the
-      // sums, and the results, do not depend on GA, WB or the group size; the
-      // (i, j) of an element advances incrementally
-      for (int gl = 0; gl < gn; ++gl) {
-        const double* T = Ts + (int64_t)gl * N * ldt;
-        double xr = 0.0, xi = 0.0, tr = 0.0, ti = 0.0;
-        int i = ei0, j = ej0;
-        for (int e = tid; e < N * N; e += XW * 64) {
-          const double ar = T[i * ldt + j], ai = T[i * ldt + N + j];
-          const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
-          xr += ar * br - ai * bi;
-          xi += ar * bi + ai * br;
-          i += edq;
-          j += edr;
-          if (j >= N) {
-            j -= N;
-            ++i;
-          }
-        }
-        xr = wave_sum(xr);
-        xi = wave_sum(xi);
-        if (wave == gl % XW) {   // one wave adds up the diagonal (tr T)
-          for (int d = lane; d < N; d += 64) {
-            tr += T[d * ldt + d];
-            ti += T[d * ldt + N + d];
-          }
-          tr = wave_sum(tr);
-          ti = wave_sum(ti);
-        }
-        if (lane == 0) {
-          double* rr = red + (gl * XW + wave) * 4;
-          rr[0] = xr;
-          rr[1] = xi;
-          rr[2] = tr;
-          rr[3] = ti;
-        }
-      }
-      __syncthreads();
-      if (tid < gn) {
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int v = 0; v < XW; ++v)
-          for (int q = 0; q < 4; ++q) s[q] += red[(tid * XW + v) * 4 + q];
-        const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb + tid;
-        ex_re[o] = s[0];
-        ex_im[o] = s[1];
-        ell_re[o] = 2.0 * s[2];
-        ell_im[o] = 2.0 * s[3];
-      }
-    }
-  }
+  // ---- epilogue: the rows of `grp` g-blocks at a time staged in LDS
+  exchange_epilogue<double, CT * 16 + 2, 4>(
+      acc, [&](int i, int e) { return (rt0 + i) * 16 + 4 * e + lk; }, mtv, N, ga, wb, g0, w0, G1,
+      smem, grp, smem + X_LDS - X_RED, ell_re, ell_im, ex_re, ex_im);
 }
 
 template <int CT>
@@ -302,14 +228,15 @@ hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const dou
     WB = s.x_wb;
   }
   if (GA * N > X_ROWS || WB * 2 * N > X_COLS || (GA * N + 15) / 16 > XW * X_RT) return hipErrorInvalidValue;
-  // LDS: the epilogue stages grp g-blocks at a time.
+  // LDS: the epilogue stages the rows of grp g-blocks at a time (pitch
+  // 16 CT + 2 doubles).
+  const int TC = (WB * 2 * N + 15) / 16;
+  const int ct = exchange_ct(TC);
   const int avail = X_LDS - X_RED;
-  int grp = avail / (N * (2 * N + 1));
+  int grp = avail / (N * (16 * ct + 2));
   if (grp > 32) grp = 32;
   if (grp < 1) return hipErrorInvalidValue;
-  const int TC = (WB * 2 * N + 15) / 16;
-  *p = XSys{s.Lx, th_re, th_im, ell_re, ell_im, ex_re, ex_im, G1, N, s.M, W, GA, WB, grp,
-            exchange_ct(TC)};
+  *p = XSys{s.Lx, th_re, th_im, ell_re, ell_im, ex_re, ex_im, G1, N, s.M, W, GA, WB, grp, ct};
   *n_gt = (G1 + GA - 1) / GA;
   *n_wt = (W + WB - 1) / WB;
   return hipSuccess;

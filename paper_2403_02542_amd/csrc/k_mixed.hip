@@ -33,7 +33,7 @@ __global__ void k_split(const double* __restrict__ in, int64_t R, int K, int64_t
   }
 }
 
-// Theta planes [W][N][M] -> pieces of rows (w, plane, j) x Kp.
+// Theta planes [W][N][M] -> pieces of rows (w, j, plane) x Kp.
 __global__ void k_split_theta(const double* __restrict__ re, const double* __restrict__ im, int W,
                               int N, int M, int Kp, int P, int64_t piece_stride,
                               unsigned short* __restrict__ out) {
@@ -44,7 +44,7 @@ __global__ void k_split_theta(const double* __restrict__ re, const double* __res
   const int k = (int)(e - r * Kp);
   const int64_t w = r / (2 * N);
   const int rem = (int)(r - w * 2 * N);
-  const int pl = rem >= N, j = pl ? rem - N : rem;
+  const int pl = rem & 1, j = rem >> 1;
   const double* src = pl ? im : re;
   double x = k < M ? src[(w * N + j) * M + k] : 0.0;
   for (int p = 0; p < P; ++p) {
@@ -83,7 +83,7 @@ struct MxProds<3> {
 };
 
 // Lb: P pieces of the (G+1) N x Kp half-rotated blocks; tb: P pieces of
-// Theta as rows (w, plane, j) x Kp.
+// Theta as rows (w, j, plane) x Kp.
 //
 // Each wave owns its row tiles outright, so their fragments are loaded from
 // global memory straight into registers (next chunk prefetched); only the
@@ -244,84 +244,11 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
     __syncthreads();
   }
 
-  // ---- epilogue (as in the FP64 kernel), T in float64
-  float* Ts = (float*)smem;                    // T blocks in FP32 (their precision)
-  double* red = smem + red_off;               // partial sums [gl][wave][4]
-  const int ldt = twoN + 1;
-  const int ei0 = tid / N, ej0 = tid - ei0 * N;                  // element tid
-  const int edq = (MW * 64) / N, edr = MW * 64 - edq * N;     // advance per stride
-  for (int wl = 0; wl < wb; ++wl) {
-    for (int gb = 0; gb < ga; gb += grp) {
-      const int gn = min(grp, ga - gb);
-      const int rlo = gb * N, rhi = (gb + gn) * N;
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < M_RT; ++i) {
-        if (i >= mtv) continue;
-#pragma unroll
-        for (int j = 0; j < CT; ++j) {
-          if (j >= TC) continue;
-          const int c = j * 16 + lr - wl * twoN;
-          if (c < 0 || c >= twoN) continue;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int r = (rt0 + i) * 16 + (lane >> 4) * 4 + e;
-            if (r >= rlo && r < rhi) Ts[(r - rlo) * ldt + c] = acc[i][j][e];
-          }
-        }
-      }
-      __syncthreads();
-      // every g-block is cut the same way whatever the tile shape (wave w
-      // sums the elements e = w * 64 + lane (mod MW * 64) of the block), so the
-      // sums, and the results, do not depend on GA, WB or the group size; the
-      // (i, j) of an element advances incrementally
-      for (int gl = 0; gl < gn; ++gl) {
-        const float* T = Ts + (int64_t)gl * N * ldt;
-        double xr = 0.0, xi = 0.0, tr = 0.0, ti = 0.0;
-        int i = ei0, j = ej0;
-        for (int e = tid; e < N * N; e += MW * 64) {
-          const double ar = T[i * ldt + j], ai = T[i * ldt + N + j];
-          const double br = T[j * ldt + i], bi = T[j * ldt + N + i];
-          xr += ar * br - ai * bi;
-          xi += ar * bi + ai * br;
-          i += edq;
-          j += edr;
-          if (j >= N) {
-            j -= N;
-            ++i;
-          }
-        }
-        xr = wave_sum(xr);
-        xi = wave_sum(xi);
-        if (wave == gl % MW) {   // one wave adds up the diagonal (tr T)
-          for (int d = lane; d < N; d += 64) {
-            tr += T[d * ldt + d];
-            ti += T[d * ldt + N + d];
-          }
-          tr = wave_sum(tr);
-          ti = wave_sum(ti);
-        }
-        if (lane == 0) {
-          double* rr = red + (gl * MW + wave) * 4;
-          rr[0] = xr;
-          rr[1] = xi;
-          rr[2] = tr;
-          rr[3] = ti;
-        }
-      }
-      __syncthreads();
-      if (tid < gn) {
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int v = 0; v < MW; ++v)
-          for (int q = 0; q < 4; ++q) s[q] += red[(tid * MW + v) * 4 + q];
-        const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb + tid;
-        ex_re[o] = s[0];
-        ex_im[o] = s[1];
-        ell_re[o] = 2.0 * s[2];
-        ell_im[o] = 2.0 * s[3];
-      }
-    }
-  }
+  // ---- epilogue (shared with the FP64 kernel), T staged in FP32 (its
+  // precision)
+  exchange_epilogue<float, CT * 16 + 2, 6>(
+      acc, [&](int i, int e) { return (rt0 + i) * 16 + (lane >> 4) * 4 + e; }, mtv, N, ga, wb, g0,
+      w0, G1, (float*)smem, grp, smem + red_off, ell_re, ell_im, ex_re, ex_im);
 }
 
 void exchange_mx_tile(int N, int& GA, int& WB) {
@@ -360,7 +287,9 @@ hipError_t launch_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps, 
   const size_t stage_doubles = ((size_t)2 * P * CT * 16 * M_PITCH * 2 + 7) / 8;
   const size_t lds_doubles = 160 * 1024 / 8;
   if (stage_doubles > lds_doubles - red_d) return hipErrorInvalidValue;
-  int grp = (int)((lds_doubles - red_d) * 2 / ((size_t)N * (2 * N + 1)));
+  // the epilogue stages the rows of grp g-blocks at a time (FP32, pitch
+  // 16 CT + 2)
+  int grp = (int)((lds_doubles - red_d) * 2 / ((size_t)N * (16 * CT + 2)));
   if (grp > 32) grp = 32;
   if (grp < 1) return hipErrorInvalidValue;
   const int red_off = (int)(lds_doubles - red_d);
