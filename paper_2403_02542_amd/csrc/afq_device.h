@@ -681,6 +681,8 @@ constexpr size_t pipe_lds_bytes() {
 // every block (Cholesky block, walker) of the phase is reduced to
 //   X_g = sum_ij T_ij T_ji = 2 sum_{i<j} T_ij T_ji + sum_i T_ii^2,
 //   ell_g = 2 sum_i T_ii,
+// where T = (staged product) + T0_g, T0_g the real symmetric trial-space
+// block shared by the walkers,
 // with a fixed cut: thread t takes the pairs i < j of index
 // p = t + nthreads k (row by row) in the order of k, and thread t < N the
 // diagonal element t; wave sums, then the waves' partial sums in wave order.
@@ -692,14 +694,19 @@ constexpr size_t pipe_lds_bytes() {
 // The blocks of a phase are reduced up to NBMAX at a time (red holds
 // 4 NBMAX nwaves doubles).
 template <typename TS, int NB, int PITCH>
-AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, int N, double* red) {
+AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, const double* const* t0_in, int N,
+                             double* red) {
   typedef typename std::conditional<sizeof(TS) == 8, double2, float2>::type TS2;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
   const int P = N * (N - 1) / 2, twoN1 = 2 * N - 1;
   int boff[NB];
+  const double* t0[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) boff[b] = boff_in[b];
+  for (int b = 0; b < NB; ++b) {
+    boff[b] = boff_in[b];
+    t0[b] = t0_in[b];
+  }
   TS xr[NB], xi[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) xr[b] = xi[b] = (TS)0;
@@ -712,15 +719,22 @@ AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, int N, double* re
     const int j = i + 1 + p - i * (twoN1 - i) / 2;
     const int oij = i * PITCH + 2 * j, oji = j * PITCH + 2 * i;
     TS2 a[NB], c[NB];
+    TS s[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) s[b] = (TS)t0[b][i * N + j];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       a[b] = *(const TS2*)(Ts + boff[b] + oij);
       c[b] = *(const TS2*)(Ts + boff[b] + oji);
     }
+    // explicit fused multiply-adds: every instance rounds alike
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      xr[b] += a[b].x * c[b].x - a[b].y * c[b].y;
-      xi[b] += a[b].x * c[b].y + a[b].y * c[b].x;
+      const TS ar = a[b].x + s[b], br = c[b].x + s[b];
+      xr[b] = fma(ar, br, xr[b]);
+      xr[b] = fma(-a[b].y, c[b].y, xr[b]);
+      xi[b] = fma(ar, c[b].y, xi[b]);
+      xi[b] = fma(a[b].y, br, xi[b]);
     }
   }
   double dr[NB], di[NB], tr[NB], ti[NB];
@@ -731,9 +745,9 @@ AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, int N, double* re
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const TS2 d = *(const TS2*)(Ts + boff[b] + o);
-      const double x = d.x, y = d.y;
-      dr[b] = x * x - y * y;
-      di[b] = 2.0 * x * y;
+      const double x = (double)d.x + t0[b][tid * N + tid], y = d.y;
+      dr[b] = fma(x, x, -(y * y));
+      di[b] = 2.0 * (x * y);
       tr[b] = x;
       ti[b] = y;
     }
@@ -741,8 +755,8 @@ AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, int N, double* re
   double v[4 * NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    v[4 * b] = 2.0 * (double)xr[b] + dr[b];
-    v[4 * b + 1] = 2.0 * (double)xi[b] + di[b];
+    v[4 * b] = fma(2.0, (double)xr[b], dr[b]);
+    v[4 * b + 1] = fma(2.0, (double)xi[b], di[b]);
     v[4 * b + 2] = tr[b];
     v[4 * b + 3] = ti[b];
   }
@@ -762,6 +776,7 @@ AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, int N, double* re
 template <typename TS, int PITCH, int NBMAX, typename ACC, int RT, int CT, class RowOf>
 AFQ_DEV void exchange_epilogue(ACC (&acc)[RT][CT], RowOf row_of, int mtv, int N, int ga, int wb,
                                int g0, int w0, int G1, TS* Ts, int gpp, double* red,
+                               const double* __restrict__ T0,
                                double* __restrict__ ell_re, double* __restrict__ ell_im,
                                double* __restrict__ ex_re, double* __restrict__ ex_im) {
   static_assert(PITCH >= CT * 16, "pitch");
@@ -788,17 +803,19 @@ AFQ_DEV void exchange_epilogue(ACC (&acc)[RT][CT], RowOf row_of, int mtv, int N,
     for (int bb0 = 0; bb0 < nb; bb0 += NBMAX) {
       const int nbb = min(NBMAX, nb - bb0);
       int boff[NBMAX];
+      const double* t0[NBMAX];
 #pragma unroll
       for (int b = 0; b < NBMAX; ++b) {
         const int bq = b < nbb ? bb0 + b : bb0;
         const int gl = bq / wb, wl = bq - gl * wb;
         boff[b] = gl * N * PITCH + wl * twoN;
+        t0[b] = T0 + (int64_t)(g0 + gb0 + gl) * N * N;
       }
       // exactly nbb blocks: one instance per count
       switch (nbb) {
 #define AFQ_REDUCE_CASE(K)                                          \
   case K:                                                           \
-    if constexpr (K <= NBMAX) exchange_reduce<TS, K, PITCH>(Ts, boff, N, red); \
+    if constexpr (K <= NBMAX) exchange_reduce<TS, K, PITCH>(Ts, boff, t0, N, red); \
     break;
         AFQ_REDUCE_CASE(1)
         AFQ_REDUCE_CASE(2)

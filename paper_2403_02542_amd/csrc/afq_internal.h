@@ -30,6 +30,15 @@ struct SysDev {
   // trial
   double* psit = nullptr;     // [N][M]   Psi_T^T
   double* Lx = nullptr;       // [(G+1)][N][M]: Psi_T^T L_g for g < G, Psi_T^T h for g = G
+  // virtual space: Psi_perp, an orthonormal complement of the trial orbitals
+  // ([Kv][M], one vector per row, Kv = M - N); the blocks restricted to it
+  // Psi_T^T L_g Psi_perp ([(G+1)][N][Kv]) and to the trial space
+  // T0_g = Psi_T^T L_g Psi_T ([(G+1)][N][N]); with Theta = Psi_T + Psi_perp
+  // Theta_v, T_g = T0_g + (Psi_T^T L_g Psi_perp) Theta_v
+  int Kv = 0;
+  double* psiv = nullptr;
+  double* Lov = nullptr;
+  double* T0 = nullptr;
   double* lbar = nullptr;     // [G]
   double* H1 = nullptr;       // [M][M]
   double* Bhalf = nullptr;    // [M][M] exp(-tau H1 / 2)
@@ -42,6 +51,7 @@ struct SysDev {
   double *phi_re = nullptr, *phi_im = nullptr;     // [W][N][M]
   double *phn_re = nullptr, *phn_im = nullptr;     // next-step orbitals
   double *th_re = nullptr, *th_im = nullptr;       // Theta = Phi (Psi_T^T Phi)^-1
+  double *thv_re = nullptr, *thv_im = nullptr;     // [W][N][Kv] Theta_v = Psi_perp^T Theta
   double *thn_re = nullptr, *thn_im = nullptr;
   double* logdet = nullptr;   // [W][2]
   double* logdet_n = nullptr; // [W][2]
@@ -89,9 +99,9 @@ struct SysDev {
   // mixed precision (BF16-split) operands
   int mx_pieces = 0;          // pieces of the current split arrays (0 = none)
   int Kp = 0;                 // K (= M) padded to a multiple of 32
-  unsigned short* Lxb = nullptr;  // [P][(G+1) N][Kp] pieces of the half-rotated blocks
+  unsigned short* Lxb = nullptr;  // [P][(G+1) N][Kp] pieces of Psi_T^T L_g Psi_perp (K = Kv)
   int64_t Lxb_ps = 0;
-  unsigned short* thb = nullptr;  // [P][W 2N][Kp] pieces of Theta
+  unsigned short* thb = nullptr;  // [P][W 2N][Kp] pieces of Theta_v
   int64_t thb_ps = 0;
   // BF16 pieces of the operator build, the one-body half-steps and the
   // operator-orbital products of the current propagate call (0 = FP64)
@@ -139,16 +149,18 @@ struct CallState {
 };
 
 // One system's operands of the local-energy contraction (also one entry of
-// a many-system launch).  ct: column tiles of its kernel instance.
+// a many-system launch): T_g^w = T0_g + Lov_g Theta_v^w over K = M - N.
+// ct: column tiles of its kernel instance.
 struct XSys {
-  const double* Lx;
-  const double* th_re;
-  const double* th_im;
+  const double* Lov;
+  const double* T0;
+  const double* thv_re;
+  const double* thv_im;
   double* ell_re;
   double* ell_im;
   double* ex_re;
   double* ex_im;
-  int G1, N, M, W, GA, WB, grp, ct;
+  int G1, N, K, W, GA, WB, grp, ct;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -228,13 +240,17 @@ hipError_t launch_weight(SysDev& s, double tau, const double* qr_logr, hipStream
 hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st,
                      const CallState* cs = nullptr, int add = 0, int every = 0);
 hipError_t launch_commit(SysDev& s, hipStream_t st);
-// Local energy of W walkers with Green's functions (th_re, th_im).
+// Theta_v = Psi_perp^T Theta of W walkers: [W][N][Kv] per plane.
+hipError_t launch_project(const SysDev& s, int W, const double* th_re, const double* th_im,
+                          double* thv_re, double* thv_im, hipStream_t st);
+// Local energy of W walkers with Green's functions (th_re, th_im); the
+// virtual-space part Theta_v goes to (thv_re, thv_im), [W][N][Kv] each.
 hipError_t launch_exchange(SysDev& s, int W, const double* th_re, const double* th_im,
-                           double* ell_re, double* ell_im, double* ex_re, double* ex_im,
-                           hipStream_t st);
-// Operands and grid of one system's contraction (tile shape from the tuner
-// when set, else from the occupancy model).
-hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const double* th_im,
+                           double* thv_re, double* thv_im, double* ell_re, double* ell_im,
+                           double* ex_re, double* ex_im, hipStream_t st);
+// Operands and grid of one system's contraction from Theta_v (tile shape from
+// the tuner when set, else from the occupancy model).
+hipError_t exchange_setup(const SysDev& s, int W, const double* thv_re, const double* thv_im,
                           double* ell_re, double* ell_im, double* ex_re, double* ex_im, XSys* p,
                           int* n_gt, int* n_wt);
 // Tiles (gt, wt) of one system in the single-system launch order.
@@ -301,3 +317,6 @@ hipError_t launch_fb_adjoint_into(SysDev& s, const double* d_ell, double* grad_L
 // destroyed; evals ascending, evecs column j = eigenvector j (row-major).
 void jacobi_eigh(int n, std::vector<double>& a, std::vector<double>& evals,
                  std::vector<double>& evecs);
+// Orthonormal complement of the orthonormal columns of psi (m x n,
+// row-major): out[(c - n) m + p], one vector per row (Householder QR).
+void complement_basis(int m, int n, const std::vector<double>& psi, std::vector<double>& out);

@@ -236,7 +236,7 @@ afq_status ensure_mixed(afq_ctx* ctx, int32_t sid, SysDev& s, int pieces) {
   if (s.mx_pieces == pieces && s.Lxb && s.thb) return AFQ_OK;
   auto& own = ctx->sys_allocs[sid];
   auto& wown = s.walker_allocs;
-  s.Kp = (s.M + 31) / 32 * 32;
+  s.Kp = (s.Kv + 31) / 32 * 32;
   const int64_t rows = (int64_t)(s.G + 1) * s.N;
   if (!s.Lxb || s.mx_pieces < pieces) {
     TRY(dalloc(ctx, own, &s.Lxb, (size_t)3 * rows * s.Kp));
@@ -247,15 +247,15 @@ afq_status ensure_mixed(afq_ctx* ctx, int32_t sid, SysDev& s, int pieces) {
     s.thb_ps = (int64_t)s.W * 2 * s.N * s.Kp;
     ++s.gen;
   }
-  HIPCHK(launch_split(s.Lx, rows, s.M, s.M, s.Kp, pieces, s.Lxb_ps, s.Lxb, ctx->stream));
+  HIPCHK(launch_split(s.Lov, rows, s.Kv, s.Kv, s.Kp, pieces, s.Lxb_ps, s.Lxb, ctx->stream));
   s.mx_pieces = pieces;
   return AFQ_OK;
 }
 
 // Local energy and Coulomb vector of the current walkers (Theta in th_*).
 afq_status eval_energy(afq_ctx* ctx, SysDev& s) {
-  HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im,
-                         ctx->stream));
+  HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.thv_re, s.thv_im, s.ell_re, s.ell_im,
+                         s.ex_re, s.ex_im, ctx->stream));
   HIPCHK(launch_energy(s, s.W, s.ell_re, s.ell_im, s.ex_re, s.ex_im, s.eloc, s.ecap, s.e0s, 0.0,
                        ctx->stream));
   return AFQ_OK;
@@ -404,10 +404,12 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
 afq_status step_exchange(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, hipStream_t st) {
   Phase ph(ctx, AFQ_PH_EXCHANGE);
   if (energy_pieces(P.precision) == 0) {
-    HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
+    HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.thv_re, s.thv_im, s.ell_re, s.ell_im,
+                           s.ex_re, s.ex_im, st));
   } else {
-    HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps, s.thb,
-                              st));
+    HIPCHK(launch_project(s, s.W, s.th_re, s.th_im, s.thv_re, s.thv_im, st));
+    HIPCHK(launch_split_theta(s.thv_re, s.thv_im, s.W, s.N, s.Kv, s.Kp, s.mx_pieces, s.thb_ps,
+                              s.thb, st));
     HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
   }
   return AFQ_OK;
@@ -519,7 +521,7 @@ afq_status get_xtable(afq_ctx* ctx, const std::vector<SysDev*>& ss, afq_ctx::XTa
   std::vector<char> key;
   for (int i = 0; i < n; ++i) {
     SysDev& s = *ss[i];
-    const hipError_t e = exchange_setup(s, s.W, s.th_re, s.th_im, s.ell_re, s.ell_im, s.ex_re,
+    const hipError_t e = exchange_setup(s, s.W, s.thv_re, s.thv_im, s.ell_re, s.ell_im, s.ex_re,
                                         s.ex_im, &xs[i], &ngt[i], &nwt[i]);
     if (e != hipSuccess) return fail(ctx, AFQ_EINVAL, "local-energy tile set-up failed");
     put_bytes(key, xs[i]);
@@ -534,9 +536,9 @@ afq_status get_xtable(afq_ctx* ctx, const std::vector<SysDev*>& ss, afq_ctx::XTa
   std::vector<int4> tiles;
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  // longest tiles first (K = M), larger systems first within equal M
+  // longest tiles first (K = M - N), larger systems first within equal K
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    if (xs[a].M != xs[b].M) return xs[a].M > xs[b].M;
+    if (xs[a].K != xs[b].K) return xs[a].K > xs[b].K;
     return (int64_t)ngt[a] * nwt[a] > (int64_t)ngt[b] * nwt[b];
   });
   std::vector<int2> tl;
@@ -603,6 +605,7 @@ afq_status batch_step(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev
   if (energy_pieces(P.precision) == 0) {
     afq_ctx::XTable* tab;
     TRY(get_xtable(ctx, ss, &tab));
+    for (SysDev* s : ss) HIPCHK(launch_project(*s, s->W, s->th_re, s->th_im, s->thv_re, s->thv_im, origin));
     for (size_t c = 0; c < tab->ct.size(); ++c)
       HIPCHK(launch_exchange_group(tab->ct[c], tab->d_sys, tab->d_tiles + tab->begin[c],
                                    tab->count[c], origin));
@@ -866,6 +869,26 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
   g.B = s.h; g.C = s.Lx + (size_t)G * N * M; g.batch = 1;
   HIPCHK(launch_gemm(g, ctx->stream));
   HIPCHK(launch_lbar(s, ctx->stream));
+  // virtual space: Psi_perp (host Householder QR of Psi_T), the blocks
+  // Psi_T^T L_g Psi_perp and T0_g = Psi_T^T L_g Psi_T (g = G: h)
+  s.Kv = M - N;
+  {
+    std::vector<double> pv;
+    complement_basis(M, N, psi, pv);
+    TRY(dalloc(ctx, own, &s.psiv, pv.size()));
+    TRY(dalloc(ctx, own, &s.Lov, (size_t)(G + 1) * N * s.Kv));
+    TRY(dalloc(ctx, own, &s.T0, (size_t)(G + 1) * N * N));
+    if (!pv.empty())
+      HIPCHK(hipMemcpy(s.psiv, pv.data(), pv.size() * 8, hipMemcpyHostToDevice));
+    GemmArgs q{};
+    q.A = s.Lx; q.sAb = 0; q.sAr = M; q.sAk = 1; q.sAkb = 0;
+    q.B = s.psiv; q.sBb = 0; q.sBc = M; q.sBk = 1; q.sBkb = 0;
+    q.C = s.Lov; q.sCb = 0; q.sCr = s.Kv; q.sCc = 1;
+    q.R = (G + 1) * N; q.Cn = s.Kv; q.K = M; q.kin = M; q.batch = 1; q.alpha = 1.0; q.beta = 0.0;
+    HIPCHK(launch_gemm(q, ctx->stream));
+    q.B = s.psit; q.C = s.T0; q.sCr = N; q.Cn = N;
+    HIPCHK(launch_gemm(q, ctx->stream));
+  }
   // H1 = h - 1/2 sum_g L_g L_g + sum_g Lbar_g L_g
   HIPCHK(hipMemcpyAsync(s.H1, s.h, MM * 8, hipMemcpyDeviceToDevice, ctx->stream));
   // sum_g L_g L_g in chunks of 32 Cholesky vectors: shorter sequential sums
@@ -896,11 +919,13 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
   s.tau_b = -1.0;
   // trial energy E_L(Psi_T): Theta = Psi_T for one walker
   std::vector<void*> tmp;
-  double *tre, *tim, *lr, *li, *xr, *xi, *el;
+  double *tre, *tim, *vre, *vim, *lr, *li, *xr, *xi, *el;
   afq_status r = AFQ_OK;
   const size_t G1 = (size_t)G + 1;
   if (r == AFQ_OK) r = dalloc(ctx, tmp, &tre, (size_t)N * M);
   if (r == AFQ_OK) r = dalloc(ctx, tmp, &tim, (size_t)N * M);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &vre, (size_t)N * s.Kv);
+  if (r == AFQ_OK) r = dalloc(ctx, tmp, &vim, (size_t)N * s.Kv);
   if (r == AFQ_OK) r = dalloc(ctx, tmp, &lr, G1);
   if (r == AFQ_OK) r = dalloc(ctx, tmp, &li, G1);
   if (r == AFQ_OK) r = dalloc(ctx, tmp, &xr, G1);
@@ -913,7 +938,7 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
   hipError_t e = hipMemcpyAsync(tre, s.psit, (size_t)N * M * 8, hipMemcpyDeviceToDevice, ctx->stream);
   std::vector<double> zeros((size_t)N * M, 0.0);
   if (e == hipSuccess) e = hipMemcpy(tim, zeros.data(), zeros.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_exchange(s, 1, tre, tim, lr, li, xr, xi, ctx->stream);
+  if (e == hipSuccess) e = launch_exchange(s, 1, tre, tim, vre, vim, lr, li, xr, xi, ctx->stream);
   if (e == hipSuccess) e = launch_energy(s, 1, lr, li, xr, xi, el, nullptr, nullptr, 0.0, ctx->stream);
   double eh[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(eh, el, 16, hipMemcpyDeviceToHost, ctx->stream);
@@ -956,6 +981,8 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   double** planes[] = {&s.phi_re, &s.phi_im, &s.phn_re, &s.phn_im, &s.th_re, &s.th_im, &s.thn_re,
                        &s.thn_im, &s.t1_re, &s.t1_im, &s.t2_re, &s.t2_im, &s.t3_re, &s.t3_im};
   for (double** p : planes) TRY(dalloc(ctx, own, p, W * NM));
+  TRY(dalloc(ctx, own, &s.thv_re, W * s.N * s.Kv));
+  TRY(dalloc(ctx, own, &s.thv_im, W * s.N * s.Kv));
   TRY(dalloc(ctx, own, &s.logdet, W * 2));
   TRY(dalloc(ctx, own, &s.logdet_n, W * 2));
   TRY(dalloc(ctx, own, &s.weight, W));
@@ -1154,7 +1181,8 @@ afq_status afq_autotune(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_sys, int
       s.x_ga = c.x;
       s.x_wb = c.y;
       float ms = 0.f;
-      r = time_it([&] { return launch_exchange(s, s.W, s.th_re, s.th_im, lr, li, xr, xi, ctx->stream); },
+      r = time_it([&] { return launch_exchange(s, s.W, s.th_re, s.th_im, s.thv_re, s.thv_im, lr, li,
+                                               xr, xi, ctx->stream); },
                   &ms);
       if (r != AFQ_OK) break;
       if (ms < best) {
@@ -1220,8 +1248,9 @@ afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precisio
       TRY(dalloc(ctx, s.walker_allocs, &s.mex_re, n));
       TRY(dalloc(ctx, s.walker_allocs, &s.mex_im, n));
     }
-    HIPCHK(launch_split_theta(s.th_re, s.th_im, s.W, s.N, s.M, s.Kp, s.mx_pieces, s.thb_ps, s.thb,
-                              ctx->stream));
+    HIPCHK(launch_project(s, s.W, s.th_re, s.th_im, s.thv_re, s.thv_im, ctx->stream));
+    HIPCHK(launch_split_theta(s.thv_re, s.thv_im, s.W, s.N, s.Kv, s.Kp, s.mx_pieces, s.thb_ps,
+                              s.thb, ctx->stream));
     HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.mell_re, s.mell_im, s.mex_re, s.mex_im,
                               ctx->stream));
     HIPCHK(launch_energy(s, s.W, s.mell_re, s.mell_im, s.mex_re, s.mex_im, s.eloc, nullptr,
@@ -1266,7 +1295,8 @@ afq_status afq_local_energy_batch_noalloc(afq_ctx* ctx, int32_t sys_id, double* 
   double* xi = xr + n;
   // every element of the four planes is written by the contraction: nothing
   // needs clearing between calls
-  HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, lr, li, xr, xi, ctx->stream));
+  HIPCHK(launch_exchange(s, s.W, s.th_re, s.th_im, s.thv_re, s.thv_im, lr, li, xr, xi,
+                         ctx->stream));
   HIPCHK(launch_energy(s, s.W, lr, li, xr, xi, eloc_out, nullptr, nullptr, 0.0, ctx->stream));
   if (ell_out) HIPCHK(launch_pack_complex(lr, li, s.W, s.G + 1, s.G, ell_out, ctx->stream));
   return AFQ_OK;

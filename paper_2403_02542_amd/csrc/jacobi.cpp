@@ -1,7 +1,9 @@
-// Host symmetric eigensolver: cyclic Jacobi rotations (Golub & Van Loan,
-// "Matrix Computations", symmetric Schur decomposition).  Used once per
-// system to diagonalise the one-body matrix H1, so that the half-step
-// exp(-tau H1 / 2) of the Split-2 propagator is exact (Sec. III.A-B).
+// Host linear algebra of the set-up: a symmetric eigensolver by cyclic
+// Jacobi rotations (Golub & Van Loan, "Matrix Computations", symmetric Schur
+// decomposition), used once per system to diagonalise the one-body matrix
+// H1 so that the half-step exp(-tau H1 / 2) of the Split-2 propagator is
+// exact (Sec. III.A-B); and an orthonormal complement of the trial orbitals
+// from a Householder QR.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -66,5 +68,47 @@ void jacobi_eigh(int n, std::vector<double>& a, std::vector<double>& evals,
   for (int j = 0; j < n; ++j) {
     evals[j] = A(idx[j], idx[j]);
     for (int k = 0; k < n; ++k) evecs[(size_t)k * n + j] = v[(size_t)k * n + idx[j]];
+  }
+}
+
+// Orthonormal basis of the orthogonal complement of the columns of psi
+// (m x n, row-major, orthonormal columns), from the Householder QR of psi:
+// Q = H_0 H_1 ... H_{n-1}, and the complement is Q e_c for c = n .. m-1.
+// out[(c - n) * m + p] = Q[p][c] (one complement vector per row).
+void complement_basis(int m, int n, const std::vector<double>& psi, std::vector<double>& out) {
+  std::vector<double> a(psi);                    // reduced in place
+  std::vector<double> vs((size_t)n * m, 0.0);    // reflector k in row k (entries k..m-1)
+  std::vector<double> beta(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double nrm = 0.0;
+    for (int p = k; p < m; ++p) nrm += a[(size_t)p * n + k] * a[(size_t)p * n + k];
+    nrm = std::sqrt(nrm);
+    const double x0 = a[(size_t)k * n + k];
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    double* v = &vs[(size_t)k * m];
+    for (int p = k; p < m; ++p) v[p] = a[(size_t)p * n + k];
+    v[k] -= alpha;
+    double vv = 0.0;
+    for (int p = k; p < m; ++p) vv += v[p] * v[p];
+    beta[k] = vv > 0.0 ? 2.0 / vv : 0.0;
+    for (int c = k; c < n; ++c) {   // apply H_k = I - beta v v^T to the remaining columns
+      double s = 0.0;
+      for (int p = k; p < m; ++p) s += v[p] * a[(size_t)p * n + c];
+      s *= beta[k];
+      for (int p = k; p < m; ++p) a[(size_t)p * n + c] -= s * v[p];
+    }
+  }
+  out.assign((size_t)(m - n) * m, 0.0);
+  std::vector<double> q(m);
+  for (int c = n; c < m; ++c) {
+    for (int p = 0; p < m; ++p) q[p] = p == c ? 1.0 : 0.0;
+    for (int k = n - 1; k >= 0; --k) {
+      const double* v = &vs[(size_t)k * m];
+      double s = 0.0;
+      for (int p = k; p < m; ++p) s += v[p] * q[p];
+      s *= beta[k];
+      for (int p = k; p < m; ++p) q[p] -= s * v[p];
+    }
+    for (int p = 0; p < m; ++p) out[(size_t)(c - n) * m + p] = q[p];
   }
 }

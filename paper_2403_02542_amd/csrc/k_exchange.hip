@@ -1,10 +1,15 @@
 // Local-energy contraction (Eq. eloc, Cholesky form) on the FP64 matrix cores.
 //
-// For every walker w and Cholesky block g (g < G: Psi_T^T L_g; g = G:
-// Psi_T^T h), T_g^w = (Psi_T^T L_g) Theta^w is an N x N complex matrix.
+// For every walker w and Cholesky block g (g < G: L_g; g = G: h),
+// T_g^w = Psi_T^T L_g Theta^w is an N x N complex matrix.  Since
+// Psi_T^T Theta = I, Theta = Psi_T + Psi_perp Theta_v with Psi_perp an
+// orthonormal complement of the trial orbitals, and
+//   T_g^w = T0_g + (Psi_T^T L_g Psi_perp) Theta_v^w,  T0_g = Psi_T^T L_g Psi_T,
+// a product over the virtual space only (K = M - N).
 // The kernel never stores T: a 512-thread workgroup computes the T blocks
 // of GA consecutive g-blocks and WB consecutive walkers as one MFMA tile
-//   rows (g, i): GA N,   columns (w, j, plane): WB 2N,   K = M,
+//   rows (g, i): GA N,   columns (w, j, plane): WB 2N,   K = M - N,
+// the epilogue adding T0 (real, symmetric),
 // then stages the tile in LDS a few blocks at a time and reduces every
 // N x N block (exchange_epilogue) to
 //   ell_g = 2 tr T_g        (the mixed <Lhat_g>, also the next force bias)
@@ -43,10 +48,10 @@ constexpr int X_SUPER_G = 4, X_SUPER_W = 8;         // super-tile per XCD
 // One tile (g-tile gt, walker tile wt) of one system.
 template <int CT>
 __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt, double* smem) {
-  const int G1 = p.G1, N = p.N, M = p.M, W = p.W, GA = p.GA, WB = p.WB, grp = p.grp;
-  const double* __restrict__ Lx = p.Lx;
-  const double* __restrict__ th_re = p.th_re;
-  const double* __restrict__ th_im = p.th_im;
+  const int G1 = p.G1, N = p.N, M = p.K, W = p.W, GA = p.GA, WB = p.WB, grp = p.grp;
+  const double* __restrict__ Lx = p.Lov;
+  const double* __restrict__ th_re = p.thv_re;
+  const double* __restrict__ th_im = p.thv_im;
   double* __restrict__ ell_re = p.ell_re;
   double* __restrict__ ell_im = p.ell_im;
   double* __restrict__ ex_re = p.ex_re;
@@ -97,6 +102,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
     }
   };
 
+  const int lr = lane & 15, lk = lane >> 4;
   d4_t acc[X_RT][CT];
 #pragma unroll
   for (int i = 0; i < X_RT; ++i)
@@ -109,7 +115,6 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
   // (column tiles TC..CT-1 of the stage hold zeros, so their MFMAs are wasted
   // but harmless; the occupancy model prices them in)
   const bool full = CT < 10 && mtv == X_RT;
-  const int lr = lane & 15, lk = lane >> 4;
   fetch(0);
   store(smem);
   __syncthreads();
@@ -158,7 +163,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
   // ---- epilogue: the rows of `grp` g-blocks at a time staged in LDS
   exchange_epilogue<double, CT * 16 + 2, 4>(
       acc, [&](int i, int e) { return (rt0 + i) * 16 + 4 * e + lk; }, mtv, N, ga, wb, g0, w0, G1,
-      smem, grp, smem + X_LDS - X_RED, ell_re, ell_im, ex_re, ex_im);
+      smem, grp, smem + X_LDS - X_RED, p.T0, ell_re, ell_im, ex_re, ex_im);
 }
 
 template <int CT>
@@ -216,7 +221,7 @@ void exchange_tile(int N, int& GA, int& WB) {
 
 }  // namespace
 
-hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const double* th_im,
+hipError_t exchange_setup(const SysDev& s, int W, const double* thv_re, const double* thv_im,
                           double* ell_re, double* ell_im, double* ex_re, double* ex_im, XSys* p,
                           int* n_gt, int* n_wt) {
   const int N = s.N, G1 = s.G + 1;
@@ -236,7 +241,8 @@ hipError_t exchange_setup(const SysDev& s, int W, const double* th_re, const dou
   int grp = avail / (N * (16 * ct + 2));
   if (grp > 32) grp = 32;
   if (grp < 1) return hipErrorInvalidValue;
-  *p = XSys{s.Lx, th_re, th_im, ell_re, ell_im, ex_re, ex_im, G1, N, s.M, W, GA, WB, grp, ct};
+  *p = XSys{s.Lov, s.T0, thv_re, thv_im, ell_re, ell_im, ex_re, ex_im, G1, N, s.Kv, W, GA, WB,
+            grp, ct};
   *n_gt = (G1 + GA - 1) / GA;
   *n_wt = (W + WB - 1) / WB;
   return hipSuccess;
@@ -280,12 +286,32 @@ hipError_t run_exchange_group(const XSys* d_sys, const int4* d_tiles, int n_tile
 
 }  // namespace
 
+hipError_t launch_project(const SysDev& s, int W, const double* th_re, const double* th_im,
+                          double* thv_re, double* thv_im, hipStream_t st) {
+  if (s.Kv == 0) return hipSuccess;
+  // rows (w, j) of Theta (K = M) times the complement vectors
+  const double* in[2] = {th_re, th_im};
+  double* out[2] = {thv_re, thv_im};
+  for (int pl = 0; pl < 2; ++pl) {
+    GemmArgs g{};
+    g.A = in[pl]; g.sAb = 0; g.sAr = s.M; g.sAk = 1; g.sAkb = 0;
+    g.B = s.psiv; g.sBb = 0; g.sBc = s.M; g.sBk = 1; g.sBkb = 0;
+    g.C = out[pl]; g.sCb = 0; g.sCr = s.Kv; g.sCc = 1;
+    g.R = W * s.N; g.Cn = s.Kv; g.K = s.M; g.kin = s.M; g.batch = 1; g.alpha = 1.0; g.beta = 0.0;
+    const hipError_t e = launch_gemm(g, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_exchange(SysDev& s, int W, const double* th_re, const double* th_im,
-                           double* ell_re, double* ell_im, double* ex_re, double* ex_im,
-                           hipStream_t st) {
+                           double* thv_re, double* thv_im, double* ell_re, double* ell_im,
+                           double* ex_re, double* ex_im, hipStream_t st) {
+  hipError_t e = launch_project(s, W, th_re, th_im, thv_re, thv_im, st);
+  if (e != hipSuccess) return e;
   XSys p;
   int n_gt, n_wt;
-  hipError_t e = exchange_setup(s, W, th_re, th_im, ell_re, ell_im, ex_re, ex_im, &p, &n_gt, &n_wt);
+  e = exchange_setup(s, W, thv_re, thv_im, ell_re, ell_im, ex_re, ex_im, &p, &n_gt, &n_wt);
   if (e != hipSuccess) return e;
   switch (p.ct) {
     case 4: return run_exchange<4>(p, n_gt, n_wt, st);

@@ -5,8 +5,9 @@
 //
 //  * k_split: float64 planes -> P bfloat16 piece planes, rows padded to Kp.
 //  * k_exchange_mx: the local-energy contraction of k_exchange.hip with the
-//    T_g blocks formed from BF16-split (Psi_T^T L_g) and Theta; the N x N
-//    blocks are reduced in float64 exactly as in the FP64 kernel.
+//    virtual-space part of the T_g blocks formed from BF16-split
+//    (Psi_T^T L_g Psi_perp) and Theta_v on top of T0_g; the N x N blocks are
+//    reduced by the FP64 kernel's epilogue.
 //  * k_split_lt / k_split_av / k_opbuild_mx: the operator build A^w =
 //    sum_g a_g^w L_g from pieces of L (split once, transposed) and of the
 //    field coefficients a (split per step), writing the operator's pieces.
@@ -82,8 +83,9 @@ struct MxProds<3> {
   static constexpr int b[6] = {0, 1, 0, 1, 2, 0};
 };
 
-// Lb: P pieces of the (G+1) N x Kp half-rotated blocks; tb: P pieces of
-// Theta as rows (w, j, plane) x Kp.
+// Lb: P pieces of the (G+1) N x Kp blocks Psi_T^T L_g Psi_perp; tb: P
+// pieces of Theta_v as rows (w, j, plane) x Kp; T0: the trial-space blocks
+// the epilogue adds.
 //
 // Each wave owns its row tiles outright, so their fragments are loaded from
 // global memory straight into registers (next chunk prefetched); only the
@@ -98,7 +100,8 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
                                                      int64_t tb_ps, double* __restrict__ ell_re,
                                                      double* __restrict__ ell_im,
                                                      double* __restrict__ ex_re,
-                                                     double* __restrict__ ex_im) {
+                                                     double* __restrict__ ex_im,
+                                                     const double* __restrict__ T0) {
   extern __shared__ double smem[];
   unsigned short* lds = (unsigned short*)smem;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
   // precision)
   exchange_epilogue<float, CT * 16 + 2, 6>(
       acc, [&](int i, int e) { return (rt0 + i) * 16 + (lane >> 4) * 4 + e; }, mtv, N, ga, wb, g0,
-      w0, G1, (float*)smem, grp, smem + red_off, ell_re, ell_im, ex_re, ex_im);
+      w0, G1, (float*)smem, grp, smem + red_off, T0, ell_re, ell_im, ex_re, ex_im);
 }
 
 void exchange_mx_tile(int N, int& GA, int& WB) {
@@ -302,7 +305,7 @@ hipError_t launch_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps, 
   }
   hipLaunchKernelGGL((k_exchange_mx<CT, P>), dim3(grid), dim3(MT_), lds_doubles * 8, st, G1, N,
                      s.Kp, W, GA, WB, n_gt, n_wt, grp, red_off, s.Lxb, s.Lxb_ps, tb, tb_ps, ell_re, ell_im,
-                     ex_re, ex_im);
+                     ex_re, ex_im, s.T0);
   return hipGetLastError();
 }
 
