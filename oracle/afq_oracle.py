@@ -33,6 +33,7 @@ import scipy.linalg
 
 EXP_KRYLOV = 0
 EXP_TAYLOR = 1
+# EXP_BLOCK_KRYLOV = 2 (defined with block_krylov below)
 
 # Reading (Sec. IV.C): Arnoldi stops early ("happy breakdown") when the new
 # residual is negligible against the vector it was orthogonalised from.
@@ -242,11 +243,51 @@ def krylov(A: np.ndarray, phi: np.ndarray, k: int) -> np.ndarray:
     return out
 
 
+def block_arnoldi(A: np.ndarray, phi: np.ndarray, k: int):
+    """Block Krylov basis of span{Psi, A Psi, ..., A^(k-1) Psi} and the
+    projected operator (Eq. bkrylovsub, Sec. IV.D).
+
+    Psi = B_1 R (QR); then for j = 1..k: W = A B_j, block modified
+    Gram-Schmidt against B_1..B_j gives H_ij = B_i^dag W, and (for j < k) the
+    QR of the residual W = B_{j+1} H_{j+1,j}.  Returns (B_k (M, kN),
+    A_k (kN, kN) block upper Hessenberg, R (N, N)).  k applications of A."""
+    M, N = phi.shape
+    Q, R = np.linalg.qr(phi)
+    blocks = [Q]
+    H = np.zeros((k * N, k * N), dtype=complex)
+    for j in range(k):
+        W = A @ blocks[j]
+        for i in range(j + 1):
+            Hij = blocks[i].conj().T @ W
+            H[i * N:(i + 1) * N, j * N:(j + 1) * N] = Hij
+            W = W - blocks[i] @ Hij
+        if j + 1 == k:
+            break
+        Qn, Rn = np.linalg.qr(W)
+        H[(j + 1) * N:(j + 2) * N, j * N:(j + 1) * N] = Rn
+        blocks.append(Qn)
+    return np.hstack(blocks), H, R
+
+
+def block_krylov(A: np.ndarray, phi: np.ndarray, k: int) -> np.ndarray:
+    """bkrylov_k{A, Psi} = B_k exp(A_k) E_N R   (Eq. bkrylov)."""
+    Bk, Hk, R = block_arnoldi(A, phi, k)
+    N = phi.shape[1]
+    ENR = np.zeros((Hk.shape[0], N), dtype=complex)
+    ENR[:N, :] = R
+    return Bk @ (scipy.linalg.expm(Hk) @ ENR)
+
+
+EXP_BLOCK_KRYLOV = 2
+
+
 def exponential(A, phi, method: int, k: int):
     if method == EXP_KRYLOV:
         return krylov(A, phi, k)
     if method == EXP_TAYLOR:
         return taylor(A, phi, k)
+    if method == EXP_BLOCK_KRYLOV:
+        return block_krylov(A, phi, k)
     raise ValueError(f"unknown exponential method {method}")
 
 

@@ -651,3 +651,89 @@ def test_run_population_control_copies_walkers():
         assert np.array_equal(post[j].phi, pre[i].phi) and post[j].weight == 1.0
     est = hist[0]["estimator"]
     assert p2.e0 == pytest.approx(est[0] / est[1])
+
+
+# ---------------------------------------------------------------- block Krylov (Sec. IV.D)
+
+def _block_case(M, N, seed, scale=0.35):
+    rng = np.random.default_rng(seed)
+    S = rng.normal(size=(M, M))
+    S = (S + S.T) / math.sqrt(4 * M)
+    A = 1j * scale * S + 0.05 * np.eye(M)          # complex symmetric, like -tau H_int
+    phi = _trial(M, N, seed) + 0.3 * _rand_walker(M, N, seed)
+    return A, phi
+
+
+def test_block_krylov_full_space_is_exact():
+    """kN = M: the block Krylov space is the whole space and
+    bkrylov_k{A, Psi} = exp(A) Psi (scipy expm)."""
+    for M, N, k in ((8, 2, 4), (12, 3, 4), (10, 5, 2)):
+        A, phi = _block_case(M, N, M + N)
+        got = O.block_krylov(A, phi, k)
+        ref = scipy.linalg.expm(A) @ phi
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_block_krylov_right_equivariance():
+    """The result is V exp(V^dag A V) V^dag Psi for an orthonormal basis V of
+    the block Krylov space, so Psi -> Psi S (S invertible) gives exactly
+    bkrylov(A, Psi) S -- unlike the per-orbital Krylov."""
+    M, N, k = 20, 4, 3
+    A, phi = _block_case(M, N, 5)
+    rng = np.random.default_rng(6)
+    S = rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N))
+    a = O.block_krylov(A, phi @ S, k)
+    b = O.block_krylov(A, phi, k) @ S
+    assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+    # the per-orbital Krylov is not equivariant (the schedule of QR matters)
+    c = O.krylov(A, phi @ S, k)
+    assert np.abs(c - O.krylov(A, phi, k) @ S).max() > 1e-6
+
+
+def test_block_krylov_one_orbital_is_krylov():
+    """N = 1: the block method is the per-orbital Krylov of Eq. (krylov)."""
+    M = 16
+    A, phi = _block_case(M, 1, 9)
+    for k in (2, 4, 6):
+        a = O.block_krylov(A, phi, k)[:, 0]
+        b = O.krylov_vector(A, phi[:, 0], k)
+        assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+
+
+def test_block_arnoldi_relations():
+    """B_k^dag B_k = I, A_k = B_k^dag A B_k (Eq. projham for blocks), A_k is
+    block upper Hessenberg with upper-triangular subdiagonal blocks, and
+    Psi = B_1 R."""
+    M, N, k = 24, 3, 4
+    A, phi = _block_case(M, N, 11)
+    Bk, Hk, R = O.block_arnoldi(A, phi, k)
+    assert Bk.shape == (M, k * N) and Hk.shape == (k * N, k * N)
+    assert np.abs(Bk.conj().T @ Bk - np.eye(k * N)).max() < 1e-13
+    assert np.abs(Bk.conj().T @ A @ Bk - Hk).max() < 1e-12
+    for i in range(k):
+        for j in range(k):
+            blk = Hk[i * N:(i + 1) * N, j * N:(j + 1) * N]
+            if i > j + 1:
+                assert np.abs(blk).max() == 0.0
+            if i == j + 1:
+                assert np.abs(np.tril(blk, -1)).max() < 1e-14
+    assert np.abs(Bk[:, :N] @ R - phi).max() < 1e-13
+
+
+def test_block_krylov_thouless_and_error_decreases():
+    """Fock space: exp(Ahat)|Phi> = |bkrylov(A, Phi)> when kN = M; for
+    kN < M the error against exp(A) Phi falls with k and stays below the
+    per-orbital Krylov error at the same k."""
+    M, N = 4, 2
+    A, phi = _block_case(M, N, 13, scale=0.6)
+    ref = scipy.linalg.expm(fock.one_body(A, M).toarray()) @ fock.determinant(phi)
+    got = fock.determinant(O.block_krylov(A, phi, 2))
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    M, N = 40, 4
+    A, phi = _block_case(M, N, 14, scale=0.6)
+    exact = scipy.linalg.expm(A) @ phi
+    errs = [np.abs(O.block_krylov(A, phi, k) - exact).max() for k in (1, 2, 3, 4)]
+    assert all(errs[i + 1] < 0.5 * errs[i] for i in range(3))
+    for k in (2, 3, 4):
+        assert np.abs(O.block_krylov(A, phi, k) - exact).max() < \
+            np.abs(O.krylov(A, phi, k) - exact).max()
