@@ -45,7 +45,12 @@ enum {
   AFQ_ESTATE = 4,   /* call out of order (e.g. propagate before init_trial)     */
   AFQ_ENUMERIC = 5  /* every walker of a system is non-finite                   */
 };
-enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1 };
+/* Exponential of the one-body operator on the orbitals: per-orbital Krylov
+ * (Sec. IV.C, Eq. krylov), Taylor (Sec. IV.A, Eq. taylor), or block Krylov
+ * (Sec. IV.D, Eq. bkrylov: one kN-dimensional Krylov space per walker for
+ * all N orbitals, k N <= M; its small exponential needs one host
+ * synchronisation per step, so the graph schedule does not run it). */
+enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1, AFQ_EXP_BLOCK_KRYLOV = 2 };
 /* Precision of the dense contractions: FP64, or BF16-split operands on the
  * BF16 matrix cores with FP32 accumulation, three pieces per value (six
  * piece products, ~24 significand bits) or two pieces (three products, ~16
@@ -54,9 +59,13 @@ enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1 };
  *                half-steps (as Phi + (B - I) Phi) and the operator-orbital
  *                products of the exponential, three pieces.
  *  MIXED_FAST:   the same with two pieces.
- *  MIXED_ENERGY: only the local-energy / Coulomb-vector contraction, three
- *                pieces; propagation in FP64.
- * Overlap, inverse, QR, Arnoldi, weights and energy sums stay FP64. */
+ *  MIXED_ENERGY: only the local-energy contraction (the exchange blocks
+ *                T_g and the one-body energy), three pieces; propagation
+ *                in FP64.
+ * The Coulomb vector (force bias, Hartree term) is FP64 in every mode, a
+ * contraction N times smaller than the exchange one, so that under
+ * MIXED_ENERGY the walkers follow the FP64 trajectory.  Overlap, inverse,
+ * QR, Arnoldi, weights and energy sums stay FP64. */
 enum { AFQ_PREC_FP64 = 0, AFQ_PREC_MIXED = 1, AFQ_PREC_MIXED_FAST = 2, AFQ_PREC_MIXED_ENERGY = 3 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
@@ -95,8 +104,9 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers,
 
 typedef struct {
   double tau;            /* imaginary time step                                  */
-  int32_t exp_method;    /* AFQ_EXP_KRYLOV or AFQ_EXP_TAYLOR                   */
-  int32_t exp_order;     /* k: Krylov dimension / Taylor order (1..16)            */
+  int32_t exp_method;    /* AFQ_EXP_KRYLOV, AFQ_EXP_TAYLOR or AFQ_EXP_BLOCK_KRYLOV */
+  int32_t exp_order;     /* k: Krylov dimension / Taylor order / block-Krylov
+                            order (1..16), the number of operator applications */
   int32_t reorth_every;  /* QR after global step t when (t+1) % reorth_every == 0 */
   int32_t precision;     /* AFQ_PREC_*: FP64, MIXED, MIXED_FAST or MIXED_ENERGY  */
   int32_t n_steps;       /* steps to run                                         */

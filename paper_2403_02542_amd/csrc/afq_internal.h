@@ -73,6 +73,17 @@ struct SysDev {
   double *t3_re = nullptr, *t3_im = nullptr;
   int kmax = 0;
   double *kb_re = nullptr, *kb_im = nullptr;       // [W][N][kmax][M] Krylov basis
+  // block Krylov (the basis reuses kb as [W][kmax N][M]): projected operator
+  // [W][kb_k N][kb_k N], R [W][N][N], two [W][N][kb_k N] sets of the small
+  // exponential, the QR flags and log det R; kb_k is the order allocated for
+  int bk_k = 0;
+  double *bkh_re = nullptr, *bkh_im = nullptr;
+  double *bkr_re = nullptr, *bkr_im = nullptr;
+  double *bkx_re = nullptr, *bkx_im = nullptr, *bky_re = nullptr, *bky_im = nullptr;
+  double *bkz_re = nullptr, *bkz_im = nullptr;
+  int* bk_bad = nullptr;
+  double* bk_logr = nullptr;
+  unsigned long long* bk_norm = nullptr;
   double* kh = nullptr;       // [W][N][kmax][kmax][2] Hessenberg
   double* kbeta = nullptr;    // [W][N]
   int* kdim = nullptr;        // [W][N]
@@ -201,6 +212,8 @@ struct VecOut {
   int64_t sw, sj;
 };
 hipError_t launch_opbuild(SysDev& s, hipStream_t st);
+// out = A v over all walkers (the operator-orbital product of the exponentials).
+hipError_t launch_matvec(SysDev& s, VecRef v, VecOut o, hipStream_t st);
 // Origins of the R x 16 blocks of an M x M symmetric matrix that hold an
 // element on or above the diagonal, row blocks outermost.
 void op_blocks(int M, int R, std::vector<int2>& out);
@@ -239,7 +252,18 @@ hipError_t launch_weight(SysDev& s, double tau, const double* qr_logr, hipStream
 // step reorthonormalises (qr_logr = 0 when it does not).
 hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st,
                      const CallState* cs = nullptr, int add = 0, int every = 0);
+// The same factorisation of W orbital sets at walker stride sw (doubles);
+// failures are marked in bad[W] (the walker store's flags are left alone).
+hipError_t launch_qr_strided(SysDev& s, double* ph_re, double* ph_im, int64_t sw, double* logr,
+                             int* bad, hipStream_t st);
 hipError_t launch_commit(SysDev& s, hipStream_t st);
+// Block-Krylov exponential (Eq. bkrylov): out = B_k exp(A_k) E_N R of every
+// walker's orbital set `in`; wv is a [W][N][M] scratch pair.  Synchronises the
+// stream once (the substep count of the small exponential is chosen on the
+// host from the largest 1-norm of the A_k).
+hipError_t launch_block_krylov(SysDev& s, int k, const double* in_re, const double* in_im,
+                               double* out_re, double* out_im, double* wv_re, double* wv_im,
+                               hipStream_t st);
 // Theta_v = Psi_perp^T Theta of W walkers: [W][N][Kv] per plane.
 hipError_t launch_project(const SysDev& s, int W, const double* th_re, const double* th_im,
                           double* thv_re, double* thv_im, hipStream_t st);
@@ -266,12 +290,13 @@ int matvec_max_blocks(int M);
 // One operator-orbital product out = A in over all walkers (tuner probe).
 hipError_t launch_matvec_probe(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                                double* out_im, hipStream_t st);
-// Coulomb vector alone (ell of every walker and Cholesky block, no exchange
-// term), for the steps that do not measure the energy.  part: scratch of
-// coulomb_slices(W, G, N M) x W x G doubles.
+// Coulomb vector alone in FP64 (ell of every walker and Cholesky block into
+// ell_re / ell_im [W][G + 1], the one-body entry g = G left alone), for the
+// steps that do not measure the energy and after a BF16-split local energy.
+// part: scratch of coulomb_slices(W, G, N M) x W x G doubles.
 int coulomb_slices(int W, int G, int NM);
 hipError_t launch_coulomb(SysDev& s, const double* th_re, const double* th_im, double* part,
-                          hipStream_t st);
+                          double* ell_re, double* ell_im, hipStream_t st);
 // Admissible (GA, WB) tile shapes for N, best first by the occupancy model.
 void exchange_candidates(int N, std::vector<int2>& out);
 hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* ell_im,

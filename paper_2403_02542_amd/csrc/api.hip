@@ -217,6 +217,36 @@ afq_status ensure_krylov(afq_ctx* ctx, int32_t sid, SysDev& s, int k) {
   return AFQ_OK;
 }
 
+// Split-K scratch of the FP64 Coulomb vector.
+afq_status ensure_coulomb(afq_ctx* ctx, SysDev& s) {
+  if (s.coul_ws) return AFQ_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const size_t n = (size_t)coulomb_slices(s.W, s.G, s.N * s.M) * s.W * s.G;
+  TRY(dalloc(ctx, s.walker_allocs, &s.coul_ws, n));
+  ++s.gen;
+  return AFQ_OK;
+}
+
+// Buffers of the block-Krylov exponential of order k (kept for larger k).
+afq_status ensure_bkrylov(afq_ctx* ctx, SysDev& s, int k) {
+  if (k <= s.bk_k) return AFQ_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  auto& own = s.walker_allocs;
+  const size_t W = s.W, N = s.N, D = (size_t)k * N;
+  TRY(dalloc(ctx, own, &s.bkh_re, W * D * D));
+  TRY(dalloc(ctx, own, &s.bkh_im, W * D * D));
+  TRY(dalloc(ctx, own, &s.bkr_re, W * N * N));
+  TRY(dalloc(ctx, own, &s.bkr_im, W * N * N));
+  double** sets[] = {&s.bkx_re, &s.bkx_im, &s.bky_re, &s.bky_im, &s.bkz_re, &s.bkz_im};
+  for (double** p : sets) TRY(dalloc(ctx, own, p, W * N * D));
+  TRY(dalloc(ctx, own, &s.bk_bad, W));
+  TRY(dalloc(ctx, own, &s.bk_logr, W));
+  TRY(dalloc(ctx, own, &s.bk_norm, 1));
+  s.bk_k = k;
+  ++s.gen;
+  return AFQ_OK;
+}
+
 // BF16 pieces of the half-rotated blocks and a Theta piece buffer.
 // Block table of the symmetric FP64 operator build (made once per system,
 // on the host, before any step is captured).
@@ -359,6 +389,9 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
     Phase ph(ctx, AFQ_PH_EXPONENTIAL);
     if (P.exp_method == AFQ_EXP_KRYLOV)
       HIPCHK(launch_krylov(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re, s.t3_im, st));
+    else if (P.exp_method == AFQ_EXP_BLOCK_KRYLOV)
+      HIPCHK(launch_block_krylov(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re,
+                                 s.t3_im, st));
     else
       HIPCHK(launch_taylor(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re, s.t3_im,
                            s.phn_re, s.phn_im, st));
@@ -411,6 +444,9 @@ afq_status step_exchange(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, hipS
     HIPCHK(launch_split_theta(s.thv_re, s.thv_im, s.W, s.N, s.Kv, s.Kp, s.mx_pieces, s.thb_ps,
                               s.thb, st));
     HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
+    // the force bias of the next step (and the Hartree term) from the FP64
+    // Coulomb vector: the walkers follow the FP64 trajectory
+    HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, s.ell_re, s.ell_im, st));
   }
   return AFQ_OK;
 }
@@ -451,7 +487,7 @@ afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_para
   } else {
     // no energy this step: the next force bias needs only ell
     Phase ph(ctx, AFQ_PH_COULOMB);
-    HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, ctx->stream));
+    HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, s.ell_re, s.ell_im, ctx->stream));
   }
   TRY(step_pop(ctx, sid, s, P, t, nullptr, 0, ctx->stream));
   return AFQ_OK;
@@ -966,6 +1002,7 @@ afq_status afq_init_walkers(afq_ctx* ctx, int32_t sys_id, int64_t n_walkers, con
   free_all(s.walker_allocs);
   ++s.gen;
   s.mell_re = s.mell_im = s.mex_re = s.mex_im = nullptr;
+  s.bk_k = 0;
   s.kmax = 0;
   s.kb_re = s.kb_im = s.kh = nullptr;
   s.thb = nullptr;
@@ -1051,7 +1088,8 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   if (!ctx) return AFQ_EINVAL;
   if (!sys_ids || !P || n_sys < 1) return fail(ctx, AFQ_EINVAL, "bad arguments");
   if (!(P->tau > 0.0) || !std::isfinite(P->tau)) return fail(ctx, AFQ_EINVAL, "tau must be > 0");
-  if (P->exp_method != AFQ_EXP_KRYLOV && P->exp_method != AFQ_EXP_TAYLOR)
+  if (P->exp_method != AFQ_EXP_KRYLOV && P->exp_method != AFQ_EXP_TAYLOR &&
+      P->exp_method != AFQ_EXP_BLOCK_KRYLOV)
     return fail(ctx, AFQ_EINVAL, "unknown exp_method");
   if (P->exp_order < 1 || P->exp_order > 16) return fail(ctx, AFQ_EINVAL, "exp_order must be in [1, 16]");
   if (P->precision < AFQ_PREC_FP64 || P->precision > AFQ_PREC_MIXED_ENERGY)
@@ -1084,8 +1122,11 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
       if (sys_ids[j] == sys_ids[i]) return fail(ctx, AFQ_EINVAL, "duplicate system id");
     if (P->exp_method == AFQ_EXP_KRYLOV && ss[i]->M > 512)
       return fail(ctx, AFQ_EINVAL, "Krylov path supports M <= 512");
+    if (P->exp_method == AFQ_EXP_BLOCK_KRYLOV && P->exp_order * ss[i]->N > ss[i]->M)
+      return fail(ctx, AFQ_EINVAL, "block Krylov needs exp_order * N <= M");
     TRY(ensure_half_step(ctx, *ss[i], P->tau));
-    if (P->exp_method == AFQ_EXP_KRYLOV) TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
+    if (P->exp_method != AFQ_EXP_TAYLOR) TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
+    if (P->exp_method == AFQ_EXP_BLOCK_KRYLOV) TRY(ensure_bkrylov(ctx, *ss[i], P->exp_order));
     if (energy_pieces(P->precision))
       TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], energy_pieces(P->precision)));
     ss[i]->op_pieces = op_pieces_of(P->precision);
@@ -1110,12 +1151,7 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
         HIPCHK(launch_split_lt(s, ctx->stream));
       }
     }
-    if (P->energy_every > 1 && !ss[i]->coul_ws) {
-      SysDev& s = *ss[i];
-      const size_t n = (size_t)coulomb_slices(s.W, s.G, s.N * s.M) * s.W * s.G;
-      TRY(dalloc(ctx, s.walker_allocs, &s.coul_ws, n));
-      ++s.gen;
-    }
+    if (P->energy_every > 1 || energy_pieces(P->precision)) TRY(ensure_coulomb(ctx, *ss[i]));
     HIPCHK(launch_zero_counters(*ss[i], ctx->stream));
     if (!std::isnan(P->e0)) HIPCHK(launch_set_e0(*ss[i], P->e0, ctx->stream));
   }
@@ -1253,6 +1289,8 @@ afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precisio
                               s.thb, ctx->stream));
     HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.mell_re, s.mell_im, s.mex_re, s.mex_im,
                               ctx->stream));
+    TRY(ensure_coulomb(ctx, s));
+    HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, s.mell_re, s.mell_im, ctx->stream));
     HIPCHK(launch_energy(s, s.W, s.mell_re, s.mell_im, s.mex_re, s.mex_im, s.eloc, nullptr,
                          nullptr, 0.0, ctx->stream));
   }

@@ -395,13 +395,13 @@ int coulomb_slices(int W, int G, int NM) {
 }
 
 hipError_t launch_coulomb(SysDev& s, const double* th_re, const double* th_im, double* part,
-                          hipStream_t st) {
+                          double* ell_re, double* ell_im, hipStream_t st) {
   const int W = s.W, G = s.G, G1 = G + 1;
   const int NM = s.N * s.M;
   const int S = coulomb_slices(W, G, NM);
   const int kc = NM / S;
   const double* planes[2] = {th_re, th_im};
-  double* outs[2] = {s.ell_re, s.ell_im};
+  double* outs[2] = {ell_re, ell_im};
   for (int pl = 0; pl < 2; ++pl) {
     GemmArgs c{};
     c.A = planes[pl]; c.sAb = kc; c.sAr = NM; c.sAk = 1; c.sAkb = 0;

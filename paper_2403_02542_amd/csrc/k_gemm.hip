@@ -533,6 +533,10 @@ int matvec_default_blocks(int M) { return matvec_col_blocks(M); }
 
 int matvec_max_blocks(int M) { return (M + 15) / 16; }
 
+hipError_t launch_matvec(SysDev& s, VecRef v, VecOut o, hipStream_t st) {
+  return run_matvec(s, v, o, 0, 1.0, o, st);
+}
+
 hipError_t launch_matvec_probe(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                                double* out_im, hipStream_t st) {
   const int64_t sw = (int64_t)s.N * s.M;

@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ p
                                             int* __restrict__ bad,
                                             const int* __restrict__ alive,
                                             const CallState* __restrict__ cs, int add,
-                                            int every) {
+                                            int every, int64_t sw) {
   extern __shared__ double smem[];
   double* stage = smem;
   double* S = stage + SM_STAGE;           // N x N complex: S, then R, then R^-1
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ p
     }
   }
   if (!alive[w] || bad[w]) return;
-  const int64_t off = (int64_t)w * N * M;
+  const int64_t off = (int64_t)w * sw;   // walker stride (N M for the walker store)
   double* pr = ph_re + off;
   double* pi = ph_im + off;
   const int tid = threadIdx.x;
@@ -895,7 +895,19 @@ hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, h
   hipError_t e = allow_full_lds((const void*)k_qr, g_lds_qr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qr, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, qr_logr, s.bad,
-                     s.alive, cs, add, every);
+                     s.alive, cs, add, every, (int64_t)s.N * s.M);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_strided(SysDev& s, double* ph_re, double* ph_im, int64_t sw, double* logr,
+                             int* bad, hipStream_t st) {
+  if (2 * s.N > SM_ROWS) return hipErrorInvalidValue;
+  const size_t lds = qr_lds(s.N);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = allow_full_lds((const void*)k_qr, g_lds_qr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qr, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, logr, bad,
+                     s.alive, (const CallState*)nullptr, 0, 0, sw);
   return hipGetLastError();
 }
 
