@@ -95,17 +95,24 @@ def flags_from_info(p, info, weight_factor_ok=True):
 
 
 def run_pair(case, ctx, *, tau, k, method, reorth, n_steps, n_walkers, track, seed=0,
-             phi0=None, resync=False):
+             phi0=None, resync=False, live_only=False, stats=None):
     """Propagate n_walkers on the GPU and the `track` subset in the oracle,
     one step per call, on the same fields; returns the worst errors.
 
     resync=True restarts the oracle every step from the GPU's state, so the
-    errors are those of a single step (no accumulation along the path)."""
+    errors are those of a single step (no accumulation along the path).
+    live_only=True stops comparing a walker after the step at which its
+    oracle weight reaches zero: such a walker no longer enters any estimate,
+    and near the vanishing overlap that zeroed it, its force bias (through
+    Theta = Phi (Psi_T^T Phi)^-1) amplifies rounding step after step.
+    `stats`, a dict, receives the number of compared walker-steps."""
     import torch
     sid = case.gpu(ctx, n_walkers, phi0)
     p = case.oracle(tau)
     wks = [O.init_walker(p, None if phi0 is None else phi0[w]) for w in track]
     flagged = set()
+    dead = set()
+    compared = 0
     worst = {"phi": 0.0, "weight": 0.0, "logdet": 0.0, "eloc": 0.0}
     for s in range(n_steps):
         if resync and s > 0:
@@ -124,16 +131,27 @@ def run_pair(case, ctx, *, tau, k, method, reorth, n_steps, n_walkers, track, se
             wks[t], info = O.walker_step(p, wks[t], x[w], method, k, O.reorth_due(s, reorth))
             if flags_from_info(p, info):
                 flagged.add(w)
-            if w in flagged:
+            if w in flagged or w in dead:
                 continue
             wk = wks[t]
+            compared += 1
+            if live_only and wk.weight == 0.0:
+                dead.add(w)
             worst["phi"] = max(worst["phi"], rel(st["phi"][w], wk.phi))
             worst["weight"] = max(worst["weight"], abs(st["weight"][w] - wk.weight) / max(1.0, abs(wk.weight)))
             dl = st["log_ovlp"][w] - wk.logdet
             worst["logdet"] = max(worst["logdet"], abs(dl.real) / max(1.0, abs(wk.logdet.real)),
                                   abs(wrap(dl.imag)))
             worst["eloc"] = max(worst["eloc"], abs(el[w] - info.e_loc) / max(1.0, abs(info.e_loc)))
-        if resync or s % 5 == 4 or s == n_steps - 1:
-            print(f"  step {s + 1}/{n_steps}: worst so far {worst}, flagged {sorted(flagged)}",
+        if live_only and len(dead) == len(track):
+            print(f"  step {s + 1}/{n_steps}: every tracked walker has weight zero, stop",
                   flush=True)
+            break
+        if resync or s % 5 == 4 or s == n_steps - 1:
+            print(f"  step {s + 1}/{n_steps}: worst so far {worst}, flagged {sorted(flagged)}"
+                  + (f", weight zero from then on {sorted(dead)}" if live_only else ""),
+                  flush=True)
+    if stats is not None:
+        stats["compared"] = compared
+        stats["dead"] = sorted(dead)
     return worst, flagged, sid

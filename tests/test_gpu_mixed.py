@@ -97,8 +97,13 @@ def test_mixed_step_errors_c3():
     reach the same state by 6 FP64 steps on the same fields, then take step 7
     in FP64, MIXED_ENERGY (local energy only), MIXED and MIXED_FAST.  E_L
     errors over the walkers that still carry weight are reported as median,
-    99th percentile and maximum: a few walkers near a vanishing overlap
-    amplify the orbital rounding of the mixed propagation."""
+    99th percentile and maximum.  MIXED_ENERGY meets the 0.1 mHa bar on
+    every walker (it leaves the orbitals and weights bitwise FP64).  MIXED
+    does not: BF16-split propagation moves the orbitals by ~4e-7 relative,
+    and a few walkers near a vanishing overlap turn that into E_L
+    differences up to ~6e-4 Ha (median ~3e-6, 99th percentile ~4e-5); its
+    asserts are its own measured bounds with a margin of about 3, not the
+    bar."""
     import torch
     from paper_2403_02542_amd import afq
     C.require_gpu()
@@ -142,9 +147,10 @@ def test_mixed_step_errors_c3():
     me = errs[afq.PREC_MIXED_ENERGY]
     assert me["phi_rel_max"] == 0.0 and me["eloc_Ha_max"] < E_TOL
     mx = errs[afq.PREC_MIXED]
-    assert mx["phi_rel_max"] < 1e-6
-    assert mx["eloc_Ha_median"] < 1e-5 and mx["eloc_Ha_max"] < 1e-2
-    assert mx["weight_rel_median"] < 1e-5
+    assert mx["phi_rel_max"] < 1.5e-6
+    assert mx["eloc_Ha_median"] < 1e-5 and mx["eloc_Ha_p99"] < 1.5e-4
+    assert mx["eloc_Ha_max"] < 2e-3
+    assert mx["weight_rel_median"] < 3e-6 and mx["weight_rel_max"] < 5e-4
     fast = errs[afq.PREC_MIXED_FAST]
     assert fast["phi_rel_max"] > mx["phi_rel_max"]
 
@@ -155,9 +161,10 @@ def test_mixed_c1_both_exponentials(ctx, method, prec_name):
     """c1 (16 walkers, 20 steps, unscaled couplings) in mixed precision with
     the Taylor and the Krylov exponential vs the FP64 oracle, over every
     (walker, step) whose walker still carries weight: MIXED_ENERGY within
-    1e-4 Ha everywhere; MIXED (BF16-split propagation too) within 1e-4 Ha
-    at the 95th percentile, its outliers being walkers near a vanishing
-    overlap."""
+    1e-4 Ha everywhere (the bar); MIXED (BF16-split propagation too) misses
+    the bar on walkers near a vanishing overlap, so it is held to its own
+    measured bounds (median ~1e-6, 95th percentile ~1e-5, maximum ~1.6e-3
+    Ha) with a margin of about 3."""
     import torch
     from paper_2403_02542_amd import afq
     prec = getattr(afq, "PREC_" + prec_name)
@@ -187,7 +194,8 @@ def test_mixed_c1_both_exponentials(ctx, method, prec_name):
     if prec_name == "MIXED_ENERGY":
         assert errs.max() < E_TOL
     else:
-        assert np.median(errs) < 1e-5 and np.percentile(errs, 95) < E_TOL
+        assert np.median(errs) < 5e-6 and np.percentile(errs, 95) < 4e-5
+        assert errs.max() < 5e-3
 
 
 @pytest.mark.parametrize("M,N", [(400, 20), (396, 9)])
@@ -220,6 +228,16 @@ def test_mixed_step_large_m(M, N, method):
         c.close()
     ref, mx = res[afq.PREC_FP64], res[afq.PREC_MIXED]
     err = max(C.rel(mx["phi"][w], ref["phi"][w]) for w in range(nw))
-    print(f"M={M} N={N} {method}: MIXED orbitals max rel. {err:.2e}", flush=True)
+    # two walkers against the oracle's step on the same fields
+    p = case.oracle(0.05)
+    xh = W.fields(0, 0, 0, nw, case.G)
+    err_o = 0.0
+    for w in (0, nw - 1):
+        wk, _ = O.walker_step(p, O.init_walker(p), xh[w], em, 8, O.reorth_due(0, 1))
+        assert C.rel(ref["phi"][w], wk.phi) < C.RTOL
+        assert abs(ref["weight"][w] - wk.weight) < C.RTOL * max(1.0, wk.weight)
+        err_o = max(err_o, C.rel(mx["phi"][w], wk.phi))
+    print(f"M={M} N={N} {method}: MIXED orbitals max rel. {err:.2e} (vs FP64 kernel), "
+          f"{err_o:.2e} (vs oracle)", flush=True)
     assert np.all(np.isfinite(mx["phi"]))
-    assert err < 1e-6
+    assert err < 1e-6 and err_o < 1e-6

@@ -104,6 +104,43 @@ def test_propagation_c3_subset(ctx):
         assert v < C.RTOL, (key, v)
 
 
+@pytest.mark.parametrize("tau,steps,track,live_steps", [(0.02, 15, [5, 257], 30),
+                                                         (0.1, 15, [9, 400], 6),
+                                                         (0.05, 20, [128], 9)])
+def test_propagation_c3_tau_sweep(ctx, tau, steps, track, live_steps):
+    """The production shape at each time step of the extrapolation sweep
+    (tau = 0.02, 0.05, 0.1; 512 walkers, QR every 5 steps), oracle-tracked
+    walkers over 15-20 steps while they carry weight.  With E0 fixed at the
+    trial energy the weights of these walkers (in the oracle) stay non-zero
+    for all 15 steps at tau = 0.02, for 4 and 2 steps at tau = 0.1 and for 9
+    steps at tau = 0.05: `live_steps` walker-steps are compared."""
+    cfg = W.CONFIGS["c3"]
+    case = C.Case.from_config("c3")
+    stats = {}
+    worst, flagged, sid = C.run_pair(case, ctx, tau=tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                     reorth=cfg.reorth_every, n_steps=steps,
+                                     n_walkers=cfg.W, track=track, live_only=True, stats=stats)
+    print("c3 tau", tau, worst, "flagged", sorted(flagged), stats)
+    assert stats["compared"] == live_steps
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+@pytest.mark.parametrize("tau", [0.02, 0.1])
+def test_single_step_parity_c3_tau_sweep(ctx, tau):
+    """One-step errors at tau = 0.02 and 0.1 (oracle restarted from the GPU
+    state every step, QR steps included) for tracked walkers, with or
+    without weight, over 10 steps."""
+    cfg = W.CONFIGS["c3"]
+    case = C.Case.from_config("c3")
+    worst, flagged, sid = C.run_pair(case, ctx, tau=tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                     reorth=cfg.reorth_every, n_steps=10, n_walkers=cfg.W,
+                                     track=[9, 400], resync=True)
+    print("c3 single step tau", tau, worst, "flagged", sorted(flagged))
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
 def test_single_step_parity_c3(ctx):
     """Production shape, oracle restarted from the GPU state every step:
     the error of one step (including the QR step) is far below 1e-10."""
