@@ -174,6 +174,38 @@ struct XSys {
   int G1, N, K, W, GA, WB, grp, ct;
 };
 
+// Head and exit count of a persistent launch's device work queue (zero
+// between launches: the last block to leave resets it).
+struct WorkQ {
+  int head;
+  int done;
+};
+
+// One system's operands of the per-walker back half of a step (overlap,
+// QR, weight, commit) in a many-system persistent launch.
+struct BackSys {
+  const double* psit;
+  double* phn_re;
+  double* phn_im;
+  double* thn_re;
+  double* thn_im;
+  double* logdet_n;
+  int* bad;
+  double* qr_logr;
+  int* alive;
+  double* weight;
+  double* logdet;
+  const double* scal;
+  const E0Dev* e0s;
+  int* nfrozen;
+  const double* phi_re;
+  const double* phi_im;
+  const double* th_re;
+  const double* th_im;
+  double e_const;
+  int N, M;
+};
+
 // ------------------------------------------------------------------ launchers
 // Every launcher enqueues on `st` and returns hipGetLastError().
 
@@ -257,6 +289,12 @@ hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, h
 hipError_t launch_qr_strided(SysDev& s, double* ph_re, double* ph_im, int64_t sw, double* logr,
                              int* bad, hipStream_t st);
 hipError_t launch_commit(SysDev& s, hipStream_t st);
+// Back half of a step for many systems: one persistent launch over the
+// items (system, walker) in the given order; QR when due (from the device
+// step counter when cs is given, else qr_now).  max_n: largest N.
+hipError_t launch_back_queue(const BackSys* d_sys, const int2* d_items, int n_items, int max_n,
+                             WorkQ* q, double tau, const CallState* cs, int add, int every,
+                             bool qr_now, hipStream_t st);
 // Block-Krylov exponential (Eq. bkrylov): out = B_k exp(A_k) E_N R of every
 // walker's orbital set `in`; wv is a [W][N][M] scratch pair.  Synchronises the
 // stream once (the substep count of the small exponential is chosen on the

@@ -41,7 +41,8 @@ struct afq_ctx {
   // many-system schedule: branch streams (default priority), fork/join
   // events, the device step state of graph replays, the tile tables of the
   // many-system local-energy launches and the captured step graphs
-  static constexpr int kBranches = 4;
+  // three branches and the context stream: the four hardware queues
+  static constexpr int kBranches = 3;
   hipStream_t br[kBranches] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kBranches] = {};
@@ -53,6 +54,16 @@ struct afq_ctx {
     std::vector<int> ct, begin, count;
   };
   std::vector<XTable> xtables;
+  // item tables of the many-system back-half launch and its work queue
+  struct BTable {
+    std::vector<char> key;
+    BackSys* d_sys = nullptr;
+    int2* d_items = nullptr;
+    int n_items = 0, max_n = 0;
+  };
+  std::vector<BTable> btables;
+  static constexpr int kQueues = 4;
+  WorkQ* wq = nullptr;
   struct GraphEntry {
     std::vector<char> key;
     hipGraph_t g = nullptr;
@@ -400,6 +411,21 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
     Phase ph(ctx, AFQ_PH_ONEBODY);
     HIPCHK(launch_onebody(s, s.t2_re, s.t2_im, s.phn_re, s.phn_im, st));
   }
+  return AFQ_OK;
+}
+
+// The new orbitals' host pointers become the held ones.
+void swap_state(SysDev& s) {
+  std::swap(s.phi_re, s.phn_re);
+  std::swap(s.phi_im, s.phn_im);
+  std::swap(s.th_re, s.thn_re);
+  std::swap(s.th_im, s.thn_im);
+}
+
+// Back half of one system's step: overlap and Theta at the proposed
+// orbitals, QR when due, weights, frozen walkers restored.
+afq_status step_back(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, uint64_t t,
+                     const CallState* cs, int add, hipStream_t st) {
   {
     Phase ph(ctx, AFQ_PH_OVERLAP);
     HIPCHK(launch_overlap(s, s.W, s.phn_re, s.phn_im, s.logdet_n, s.thn_re, s.thn_im, s.bad, st));
@@ -426,10 +452,7 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
     Phase ph(ctx, AFQ_PH_WEIGHT);
     HIPCHK(launch_commit(s, st));
   }
-  std::swap(s.phi_re, s.phn_re);
-  std::swap(s.phi_im, s.phn_im);
-  std::swap(s.th_re, s.thn_re);
-  std::swap(s.th_im, s.thn_im);
+  swap_state(s);
   return AFQ_OK;
 }
 
@@ -479,6 +502,7 @@ afq_status step_system(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_para
   const uint64_t t = P.step0 + (uint64_t)si;
   const double* x = P.fields ? P.fields + (size_t)si * s.W * s.G : nullptr;
   TRY(step_front(ctx, sid, s, P, x, t, nullptr, 0, ctx->stream));
+  TRY(step_back(ctx, s, P, t, nullptr, 0, ctx->stream));
   const int every = P.energy_every > 0 ? P.energy_every : 1;
   const bool measure = (si + 1) % every == 0 || si + 1 == P.n_steps;
   if (measure) {
@@ -502,9 +526,12 @@ afq_status ensure_sched(afq_ctx* ctx) {
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_join[b], hipEventDisableTiming));
   }
   HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipMalloc(&ctx->wq, sizeof(WorkQ) * afq_ctx::kQueues));
+  HIPCHK(hipMemset(ctx->wq, 0, sizeof(WorkQ) * afq_ctx::kQueues));
   HIPCHK(hipMalloc(&ctx->cs, sizeof(CallState)));
   return AFQ_OK;
 }
+
 
 // Rough cost of one step of a system (flops), for branch balancing and the
 // order of the many-system local-energy tiles.
@@ -621,6 +648,75 @@ afq_status get_xtable(afq_ctx* ctx, const std::vector<SysDev*>& ss, afq_ctx::XTa
   return AFQ_OK;
 }
 
+// The cache of back-half item tables is bounded; tables in use are waited
+// for, and the captured graphs that hold them go with them.
+constexpr size_t kMaxBTables = 16;
+afq_status clear_btables(afq_ctx* ctx) {
+  HIPCHK(hipDeviceSynchronize());
+  clear_graphs(ctx);
+  for (auto& o : ctx->btables) {
+    (void)hipFree(o.d_sys);
+    (void)hipFree(o.d_items);
+  }
+  ctx->btables.clear();
+  return AFQ_OK;
+}
+
+// Item table of the many-system back half for the current buffer state:
+// systems by decreasing cost of their per-walker work (M N^2), each
+// system's walkers in order.
+afq_status get_btable(afq_ctx* ctx, const std::vector<SysDev*>& ss, afq_ctx::BTable** out) {
+  const int n = (int)ss.size();
+  std::vector<BackSys> bs(n);
+  std::vector<char> key;
+  int max_n = 0;
+  for (int i = 0; i < n; ++i) {
+    const SysDev& s = *ss[i];
+    bs[i] = BackSys{s.psit, s.phn_re, s.phn_im, s.thn_re, s.thn_im, s.logdet_n, s.bad,
+                    s.qr_logr, s.alive, s.weight, s.logdet, s.scal, s.e0s,
+                    s.counters ? s.counters + 3 : nullptr, s.phi_re, s.phi_im, s.th_re,
+                    s.th_im, s.e_const, s.N, s.M};
+    put_bytes(key, bs[i]);
+    put_bytes(key, s.W);
+    if (s.N > max_n) max_n = s.N;
+  }
+  for (auto& t : ctx->btables)
+    if (t.key == key) {
+      *out = &t;
+      return AFQ_OK;
+    }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (double)ss[a]->M * ss[a]->N * ss[a]->N > (double)ss[b]->M * ss[b]->N * ss[b]->N;
+  });
+  std::vector<int2> items;
+  for (int i : order)
+    for (int w = 0; w < ss[i]->W; ++w) items.push_back(int2{i, w});
+  afq_ctx::BTable t;
+  t.key = key;
+  t.n_items = (int)items.size();
+  t.max_n = max_n;
+  std::vector<void*> tmp;
+  TRY(dalloc(ctx, tmp, &t.d_sys, (size_t)n));
+  afq_status r = dalloc(ctx, tmp, &t.d_items, items.size());
+  if (r != AFQ_OK) {
+    free_all(tmp);
+    return r;
+  }
+  hipError_t e = hipMemcpy(t.d_sys, bs.data(), sizeof(BackSys) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(t.d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_all(tmp);
+    return fail(ctx, AFQ_EDEVICE, std::string("item table: ") + hipGetErrorString(e));
+  }
+  if (ctx->btables.size() >= kMaxBTables) TRY(clear_btables(ctx));
+  ctx->btables.push_back(std::move(t));
+  *out = &ctx->btables.back();
+  return AFQ_OK;
+}
+
 // One step of several systems: the per-system front halves run on the branch
 // streams, then (FP64) one local-energy launch per kernel instance covers all
 // systems, then the energies.  Host step t / row index si are used when cs
@@ -632,8 +728,21 @@ afq_status batch_step(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev
   const int nb = (int)branches.size();
   HIPCHK(hipEventRecord(ctx->ev_fork, origin));
   for (int b = 0; b < nb; ++b) HIPCHK(hipStreamWaitEvent(ctx->br[b], ctx->ev_fork, 0));
-  for (int b = 0; b < nb; ++b)
-    for (int i : branches[b]) TRY(step_front(ctx, ids[i], *ss[i], P, nullptr, t, cs, add, ctx->br[b]));
+  // per branch: the front halves of its systems one after the other, then
+  // the per-walker back halves of all of them in one persistent launch
+  const bool qr_now = !cs && reorth_due(t, P.reorth_every);
+  for (int b = 0; b < nb; ++b) {
+    std::vector<SysDev*> sub;
+    for (int i : branches[b]) {
+      TRY(step_front(ctx, ids[i], *ss[i], P, nullptr, t, cs, add, ctx->br[b]));
+      sub.push_back(ss[i]);
+    }
+    afq_ctx::BTable* bt;
+    TRY(get_btable(ctx, sub, &bt));
+    HIPCHK(launch_back_queue(bt->d_sys, bt->d_items, bt->n_items, bt->max_n, ctx->wq + b, P.tau,
+                             cs, add, P.reorth_every, qr_now, ctx->br[b]));
+    for (SysDev* s : sub) swap_state(*s);
+  }
   for (int b = 0; b < nb; ++b) {
     HIPCHK(hipEventRecord(ctx->ev_join[b], ctx->br[b]));
     HIPCHK(hipStreamWaitEvent(origin, ctx->ev_join[b], 0));
@@ -642,6 +751,10 @@ afq_status batch_step(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev
     afq_ctx::XTable* tab;
     TRY(get_xtable(ctx, ss, &tab));
     for (SysDev* s : ss) HIPCHK(launch_project(*s, s->W, s->th_re, s->th_im, s->thv_re, s->thv_im, origin));
+    // the tiles of every system: one launch per kernel instance, tiles in
+    // each system's XCD super-tile order (a persistent queue that hands
+    // tiles to whichever compute unit frees first loses that L2 locality
+    // and measured slower)
     for (size_t c = 0; c < tab->ct.size(); ++c)
       HIPCHK(launch_exchange_group(tab->ct[c], tab->d_sys, tab->d_tiles + tab->begin[c],
                                    tab->count[c], origin));
@@ -689,23 +802,26 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
     if (g.key == key) ge = &g;
   hipStream_t origin = ctx->stream;
   if (!ge) {
-    // tile tables of both buffer states first (no allocation under capture)
+    // item and tile tables of both buffer states first (no allocation
+    // under capture), with room for all of them in the cache
+    if (ctx->btables.size() + 2 * branches.size() > kMaxBTables) TRY(clear_btables(ctx));
     for (int pass = 0; pass < 2; ++pass) {
-      for (SysDev* s : ss) {
-        std::swap(s->th_re, s->thn_re);
-        std::swap(s->th_im, s->thn_im);
+      for (SysDev* s : ss) swap_state(*s);
+      afq_status r = AFQ_OK;
+      for (size_t b = 0; b < branches.size() && r == AFQ_OK; ++b) {
+        std::vector<SysDev*> sub;
+        for (int i : branches[b]) sub.push_back(ss[i]);
+        afq_ctx::BTable* bt;
+        r = get_btable(ctx, sub, &bt);
       }
-      if (energy_pieces(P.precision) == 0) {
+      if (r == AFQ_OK && energy_pieces(P.precision) == 0) {
         afq_ctx::XTable* tab;
-        afq_status r = get_xtable(ctx, ss, &tab);
-        if (r != AFQ_OK) {
-          if (pass == 0)
-            for (SysDev* s : ss) {
-              std::swap(s->th_re, s->thn_re);
-              std::swap(s->th_im, s->thn_im);
-            }
-          return r;
-        }
+        r = get_xtable(ctx, ss, &tab);
+      }
+      if (r != AFQ_OK) {
+        if (pass == 0)
+          for (SysDev* s : ss) swap_state(*s);
+        return r;
       }
     }
     afq_ctx::GraphEntry g;
@@ -805,7 +921,12 @@ void afq_destroy(afq_ctx* ctx) {
     (void)hipFree(t.d_sys);
     (void)hipFree(t.d_tiles);
   }
+  for (auto& t : ctx->btables) {
+    (void)hipFree(t.d_sys);
+    (void)hipFree(t.d_items);
+  }
   if (ctx->cs) {
+    (void)hipFree(ctx->wq);
     (void)hipDeviceSynchronize();
     (void)hipFree(ctx->cs);
     (void)hipEventDestroy(ctx->ev_fork);

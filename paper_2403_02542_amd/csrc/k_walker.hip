@@ -317,22 +317,17 @@ AFQ_DEV bool all_finite_block(bool v, double* red) {
   return block_sum(v ? 0.0 : 1.0, red) == 0.0;
 }
 
-// O = Psi_T^T Phi, log det O, Theta = Phi O^-1 per walker.
-__global__ __launch_bounds__(256) void k_overlap(int N, int M, const double* __restrict__ psit,
-                                                 const double* __restrict__ ph_re,
-                                                 const double* __restrict__ ph_im,
-                                                 double* __restrict__ logdet_out,
-                                                 double* __restrict__ th_re,
-                                                 double* __restrict__ th_im,
-                                                 int* __restrict__ bad,
-                                                 double* __restrict__ oinv_out) {
-  extern __shared__ double smem[];
+// O = Psi_T^T Phi, log det O, Theta = Phi O^-1 of walker w (one block).
+AFQ_DEV void overlap_one(int N, int M, const double* __restrict__ psit,
+                         const double* __restrict__ ph_re, const double* __restrict__ ph_im,
+                         double* __restrict__ logdet_out, double* __restrict__ th_re,
+                         double* __restrict__ th_im, int* __restrict__ bad,
+                         double* __restrict__ oinv_out, int w, double* smem) {
   double* stage = smem;
   double* X = stage + SM_STAGE;             // N x N complex
   double* fcol = X + 2 * N * N;             // 2N
   double* red = fcol + 2 * N;               // 8
   int* perm = (int*)(red + 8);              // N
-  const int w = blockIdx.x;
   const int64_t off = (int64_t)w * N * M;
   const double* pr = ph_re + off;
   const double* pi = ph_im + off;
@@ -364,18 +359,28 @@ __global__ __launch_bounds__(256) void k_overlap(int N, int M, const double* __r
   }
 }
 
+__global__ __launch_bounds__(256) void k_overlap(int N, int M, const double* __restrict__ psit,
+                                                 const double* __restrict__ ph_re,
+                                                 const double* __restrict__ ph_im,
+                                                 double* __restrict__ logdet_out,
+                                                 double* __restrict__ th_re,
+                                                 double* __restrict__ th_im,
+                                                 int* __restrict__ bad,
+                                                 double* __restrict__ oinv_out) {
+  extern __shared__ double smem[];
+  overlap_one(N, M, psit, ph_re, ph_im, logdet_out, th_re, th_im, bad, oinv_out, blockIdx.x, smem);
+}
+
 // ---------------------------------------------------------------- weights
 // log R = 2 (logdet_new - logdet_old) + s_mf;  E_H = -(log R + log I)/tau + e_const;
 // dtheta = Im log R;  m = exp(-tau (Re E_H - E0)), m >= 10 -> 0;
 // W <- W m max(0, cos dtheta).  A walker whose new state is non-finite is
 // frozen (alive = 0, W = 0); frozen walkers are never updated again.
-__global__ void k_weight(int W, double tau, const E0Dev* __restrict__ e0s, double e_const,
-                         const double* __restrict__ logdet_n, double* __restrict__ logdet,
-                         const double* __restrict__ scal, const int* __restrict__ bad,
-                         const double* __restrict__ qr_logr, int* __restrict__ alive,
-                         double* __restrict__ weight, int* __restrict__ nfrozen) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= W) return;
+AFQ_DEV void weight_one(int w, double tau, const E0Dev* __restrict__ e0s, double e_const,
+                        const double* __restrict__ logdet_n, double* __restrict__ logdet,
+                        const double* __restrict__ scal, const int* __restrict__ bad,
+                        const double* __restrict__ qr_logr, int* __restrict__ alive,
+                        double* __restrict__ weight, int* __restrict__ nfrozen) {
   if (!alive[w]) return;
   const double e0 = e0s->e0;
   if (bad[w]) {
@@ -396,6 +401,16 @@ __global__ void k_weight(int W, double tau, const E0Dev* __restrict__ e0s, doubl
   logdet[w * 2 + 1] = logdet_n[w * 2 + 1];
 }
 
+__global__ void k_weight(int W, double tau, const E0Dev* __restrict__ e0s, double e_const,
+                         const double* __restrict__ logdet_n, double* __restrict__ logdet,
+                         const double* __restrict__ scal, const int* __restrict__ bad,
+                         const double* __restrict__ qr_logr, int* __restrict__ alive,
+                         double* __restrict__ weight, int* __restrict__ nfrozen) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  weight_one(w, tau, e0s, e_const, logdet_n, logdet, scal, bad, qr_logr, alive, weight, nfrozen);
+}
+
 // ---------------------------------------------------------------- QR
 // Phi = Q R with real positive diag(R) by shifted Cholesky QR3 (Fukaya,
 // Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020): pass 0 factors
@@ -404,29 +419,14 @@ __global__ void k_weight(int W, double tau, const E0Dev* __restrict__ e0s, doubl
 // unshifted passes restore orthonormality; after every pass Phi <- Phi R^-1.
 // qr_logr[w] = sum over passes of sum_j log R_jj (so log det(Psi_T^T Phi)
 // drops by qr_logr).  A failed factorisation marks the walker bad.
-__global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ ph_re,
-                                            double* __restrict__ ph_im,
-                                            double* __restrict__ qr_logr,
-                                            int* __restrict__ bad,
-                                            const int* __restrict__ alive,
-                                            const CallState* __restrict__ cs, int add,
-                                            int every, int64_t sw) {
-  extern __shared__ double smem[];
+// Factorisation of walker w (one block); the caller skips frozen and bad walkers.
+AFQ_DEV void qr_one(int N, int M, double* __restrict__ ph_re, double* __restrict__ ph_im,
+                    double* __restrict__ qr_logr, int* __restrict__ bad, int w, int64_t sw,
+                    double* smem) {
   double* stage = smem;
   double* S = stage + SM_STAGE;           // N x N complex: S, then R, then R^-1
   double* col = S + 2 * N * N;            // 2N
   double* fail = col + 2 * N;             // failure flag of the factorisation
-  const int w = blockIdx.x;
-  if (cs) {
-    // schedule read from the device step counter: QR after step t when
-    // (t + 1) % every == 0; otherwise the step's log det R is 0
-    const uint64_t t = cs->step + (uint64_t)add;
-    if (!(every > 0 && (t + 1) % (uint64_t)every == 0)) {
-      if (threadIdx.x == 0) qr_logr[w] = 0.0;
-      return;
-    }
-  }
-  if (!alive[w] || bad[w]) return;
   const int64_t off = (int64_t)w * sw;   // walker stride (N M for the walker store)
   double* pr = ph_re + off;
   double* pi = ph_im + off;
@@ -526,14 +526,37 @@ __global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ p
   }
 }
 
-// Frozen walkers keep their held state: copy it over the proposed one.
-__global__ void k_commit(int N, int M, const int* __restrict__ alive,
-                         const double* __restrict__ ph_re, const double* __restrict__ ph_im,
-                         const double* __restrict__ th_re, const double* __restrict__ th_im,
-                         double* __restrict__ phn_re, double* __restrict__ phn_im,
-                         double* __restrict__ thn_re, double* __restrict__ thn_im) {
+// QR after step t when (t + 1) % every == 0 (step read from the device
+// counter when cs is given; otherwise the host launches only on such steps).
+AFQ_DEV bool qr_due(const CallState* cs, int add, int every) {
+  const uint64_t t = cs->step + (uint64_t)add;
+  return every > 0 && (t + 1) % (uint64_t)every == 0;
+}
+
+__global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ ph_re,
+                                            double* __restrict__ ph_im,
+                                            double* __restrict__ qr_logr,
+                                            int* __restrict__ bad,
+                                            const int* __restrict__ alive,
+                                            const CallState* __restrict__ cs, int add,
+                                            int every, int64_t sw) {
+  extern __shared__ double smem[];
   const int w = blockIdx.x;
-  if (alive[w]) return;
+  if (cs && !qr_due(cs, add, every)) {
+    // not this step: its log det R is 0
+    if (threadIdx.x == 0) qr_logr[w] = 0.0;
+    return;
+  }
+  if (!alive[w] || bad[w]) return;
+  qr_one(N, M, ph_re, ph_im, qr_logr, bad, w, sw, smem);
+}
+
+// Frozen walkers keep their held state: copy it over the proposed one.
+AFQ_DEV void commit_one(int N, int M, int w, const double* __restrict__ ph_re,
+                        const double* __restrict__ ph_im, const double* __restrict__ th_re,
+                        const double* __restrict__ th_im, double* __restrict__ phn_re,
+                        double* __restrict__ phn_im, double* __restrict__ thn_re,
+                        double* __restrict__ thn_im) {
   const int64_t off = (int64_t)w * N * M;
   for (int e = threadIdx.x; e < N * M; e += blockDim.x) {
     phn_re[off + e] = ph_re[off + e];
@@ -541,6 +564,83 @@ __global__ void k_commit(int N, int M, const int* __restrict__ alive,
     thn_re[off + e] = th_re[off + e];
     thn_im[off + e] = th_im[off + e];
   }
+}
+
+__global__ void k_commit(int N, int M, const int* __restrict__ alive,
+                         const double* __restrict__ ph_re, const double* __restrict__ ph_im,
+                         const double* __restrict__ th_re, const double* __restrict__ th_im,
+                         double* __restrict__ phn_re, double* __restrict__ phn_im,
+                         double* __restrict__ thn_re, double* __restrict__ thn_im) {
+  const int w = blockIdx.x;
+  if (alive[w]) return;
+  commit_one(N, M, w, ph_re, ph_im, th_re, th_im, phn_re, phn_im, thn_re, thn_im);
+}
+
+// ---------------------------------------------------------------- work queue
+// Next item of a persistent launch: one atomic per block, broadcast in LDS.
+AFQ_DEV int queue_next(WorkQ* q, int* slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(&q->head, 1);
+  __syncthreads();
+  const int it = *slot;
+  __syncthreads();
+  return it;
+}
+
+// Leaving a persistent launch: the last block out resets the queue for the
+// next launch (every block has taken its last item by then).
+AFQ_DEV void queue_leave(WorkQ* q) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&q->done, 1) == (int)gridDim.x - 1) {
+      atomicExch(&q->head, 0);
+      atomicExch(&q->done, 0);
+    }
+  }
+}
+
+// The per-walker back half of a step for many systems in one persistent
+// launch: item (system, walker) = overlap and Theta at the proposed
+// orbitals, the QR when due, the weight update, and the held state copied
+// over a frozen walker's proposal.  Items come from the queue in the host's
+// order (costliest systems first).
+__global__ __launch_bounds__(256) void k_back_queue(const BackSys* __restrict__ sys,
+                                                    const int2* __restrict__ items, int n_items,
+                                                    WorkQ* q, double tau,
+                                                    const CallState* __restrict__ cs, int add,
+                                                    int every, int qr_now, int ctl_off) {
+  extern __shared__ double smem[];
+  // two control words after the work area (all LDS is dynamic, so the
+  // kernel may take the whole 160 KB)
+  int& slot = ((int*)(smem + ctl_off))[0];
+  int& run = ((int*)(smem + ctl_off))[1];
+  const bool due = cs ? qr_due(cs, add, every) : qr_now != 0;
+  for (;;) {
+    const int it = queue_next(q, &slot);
+    if (it >= n_items) break;
+    const int2 d = items[it];
+    const BackSys& S = sys[d.x];
+    const int w = d.y;
+    overlap_one(S.N, S.M, S.psit, S.phn_re, S.phn_im, S.logdet_n, S.thn_re, S.thn_im, S.bad,
+                nullptr, w, smem);
+    __syncthreads();
+    if (due) {
+      if (threadIdx.x == 0) run = S.alive[w] && !S.bad[w];
+      __syncthreads();
+      if (run) qr_one(S.N, S.M, S.phn_re, S.phn_im, S.qr_logr, S.bad, w, (int64_t)S.N * S.M, smem);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      weight_one(w, tau, S.e0s, S.e_const, S.logdet_n, S.logdet, S.scal, S.bad,
+                 due ? S.qr_logr : nullptr, S.alive, S.weight, S.nfrozen);
+      run = !S.alive[w];
+    }
+    __syncthreads();
+    if (run)
+      commit_one(S.N, S.M, w, S.phi_re, S.phi_im, S.th_re, S.th_im, S.phn_re, S.phn_im, S.thn_re,
+                 S.thn_im);
+    __syncthreads();
+  }
+  queue_leave(q);
 }
 
 // ---------------------------------------------------------------- energy
@@ -908,6 +1008,34 @@ hipError_t launch_qr_strided(SysDev& s, double* ph_re, double* ph_im, int64_t sw
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qr, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, logr, bad,
                      s.alive, (const CallState*)nullptr, 0, 0, sw);
+  return hipGetLastError();
+}
+
+size_t back_lds(int N) {
+  const size_t a = overlap_lds(N), b = qr_lds(N);
+  return a > b ? a : b;
+}
+
+hipError_t launch_back_queue(const BackSys* d_sys, const int2* d_items, int n_items, int max_n,
+                             WorkQ* q, double tau, const CallState* cs, int add, int every,
+                             bool qr_now, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (2 * max_n > SM_ROWS) return hipErrorInvalidValue;
+  const size_t work = back_lds(max_n);
+  const int ctl_off = (int)((work + 7) / 8);        // in doubles
+  const size_t lds = sizeof(double) * (ctl_off + 1);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  static bool g_lds_back = false;
+  hipError_t e = allow_full_lds((const void*)k_back_queue, g_lds_back);
+  if (e != hipSuccess) return e;
+  // blocks resident at once: LDS-limited, at most 8 per compute unit
+  int per_cu = (int)((160 * 1024) / (lds + 64));
+  if (per_cu > 8) per_cu = 8;
+  if (per_cu < 1) per_cu = 1;
+  int grid = 256 * per_cu;
+  if (grid > n_items) grid = n_items;
+  hipLaunchKernelGGL(k_back_queue, dim3(grid), dim3(256), lds, st, d_sys, d_items, n_items, q,
+                     tau, cs, add, every, qr_now ? 1 : 0, ctl_off);
   return hipGetLastError();
 }
 

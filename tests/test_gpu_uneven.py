@@ -156,3 +156,63 @@ def test_largest_uneven_shape_single_step():
     print("largest uneven shape", cfg, worst, "flagged", sorted(flagged))
     for key, v in worst.items():
         assert v < C.RTOL, (key, v)
+
+
+def test_full_c4_batch_against_oracle():
+    """The whole 48-system batch (M ~ U{40..400}, N = M // 6, G = 5 M, 64
+    walkers each, Krylov 8, QR every step) in one propagate call under the
+    default many-system schedule (captured graph, persistent back-half
+    launch, many-system local energy), library fields; one oracle-tracked
+    walker on the smallest, a middle and the largest system."""
+    import torch
+    from paper_2403_02542_amd import afq
+    C.require_gpu()
+    batch = W.C4
+    cfgs = batch.configs()
+    order = np.argsort([c.M for c in cfgs], kind="stable")
+    track = {int(order[0]): 5, int(order[len(order) // 2]): 17, int(order[-1]): 63}
+    steps = 4
+    ctx = afq.Context(0)
+    ids, kept = [], {}
+    for i, cfg in enumerate(cfgs):
+        ham, psi = W.make_system(cfg, trial_iters=batch.trial_iters)
+        sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+        ctx.init_trial(sid, psi)
+        ctx.init_walkers(sid, batch.W)
+        assert sid == i
+        ids.append(sid)
+        if i in track:
+            kept[i] = (ham, psi)
+        del ham
+    print(f"  {len(ids)} systems initialised", flush=True)
+    en = torch.zeros((len(ids), steps, 2), dtype=torch.float64, device="cuda")
+    ctx.propagate_batch(ids, tau=batch.tau, n_steps=steps, exp_method=afq.EXP_KRYLOV,
+                        exp_order=batch.k, reorth_every=batch.reorth_every, seed=0,
+                        energies_out=en)
+    ctx.sync()
+    e = en.cpu().numpy()
+    assert np.all(np.isfinite(e[:, :, 1]))
+    res = {i: (ctx.get_walkers(i), ctx.local_energy_batch(i)) for i in track}
+    ctx.close()
+    compared = 0
+    for i, w in track.items():
+        cfg = cfgs[i]
+        ham, psi = kept[i]
+        p = O.prepare(ham.h, ham.L, ham.e_core, psi, batch.tau)
+        wk = O.init_walker(p)
+        flagged = False
+        for t in range(steps):
+            x = W.fields(0, i, t, batch.W, cfg.G)[w]
+            wk, info = O.walker_step(p, wk, x, O.EXP_KRYLOV, batch.k,
+                                     O.reorth_due(t, batch.reorth_every))
+            flagged = flagged or C.flags_from_info(p, info)
+        st, el = res[i]
+        print(f"  system {i} (M={cfg.M}, N={cfg.N}, G={cfg.G}) walker {w}: "
+              f"phi {C.rel(st['phi'][w], wk.phi):.2e}, flagged {flagged}", flush=True)
+        if flagged:
+            continue
+        compared += 1
+        assert C.rel(st["phi"][w], wk.phi) < C.RTOL
+        assert abs(st["weight"][w] - wk.weight) < C.RTOL * max(1.0, abs(wk.weight))
+        assert abs(el[w] - info.e_loc) < C.RTOL * max(1.0, abs(info.e_loc))
+    assert compared >= 2
