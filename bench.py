@@ -387,6 +387,25 @@ def population_rows(est):
     return out
 
 
+def run_statistics(afq, est):
+    """Time average, variance and correlation length (Sec. II.A, Eq.
+    (variance)) of the timed steps' estimates, from the library's host
+    statistics; every timed step counts (no equilibration cut), so on a short
+    run these describe the run, not a converged energy."""
+    w = np.array([den for _, den in est], dtype=np.float64)
+    e = np.array([num / den if den > 0 else 0.0 for num, den in est], dtype=np.float64)
+    live = w > 0
+    if live.sum() < 2:
+        return {"note": "fewer than two steps with weight"}
+    mean, var, n = afq.stats_time_average(w, e, 0)
+    k = afq.stats_kappa(e[live], 5.0)
+    kappa = max(1.0, k["acf"])
+    return {"e_bar": mean, "sigma_e2": var, "n": n, "kappa_acf": k["acf"],
+            "kappa_block": k["block"], "sigma_e_bar": float(np.sqrt(max(var, 0.0) * kappa / n)),
+            "note": "every timed step counted (no equilibration cut); kappa from the steps "
+                    "with weight"}
+
+
 def cpu_baseline(cfg, ham, psi, n_procs, n_steps):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     walkers are independent, so n_procs processes (one BLAS thread each, the
@@ -536,6 +555,7 @@ def main():
                 "phases": {k: {"ms_per_step": v[0] / args.steps, "launches": v[1]}
                            for k, v in prof.items()},
                 "population": population_rows(est),
+                "statistics": run_statistics(afq, est),
                 "first_step": step0 - args.steps}
 
     main_run = run_mode(args.precision)
@@ -598,6 +618,7 @@ def main():
         "roofline": main_run["roofline"],
         "phases": main_run["phases"],
         "counters": cnt,
+        "statistics": main_run["statistics"],
         "population": {"timed_steps_from": main_run["first_step"],
                        "per_step": main_run["population"],
                        "weighted_walkers_last_step": cnt["weighted"],

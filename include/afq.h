@@ -264,6 +264,54 @@ afq_status afq_profile_read(afq_ctx* ctx, double* ms_out, int64_t* launches_out,
 /* Wait for all work enqueued on the context stream. */
 afq_status afq_sync(afq_ctx* ctx);
 
+/* ---- statistics of a run's per-step estimates (host arrays; no context,
+ * no device work).  The series are the (sum W Ebar, sum W) pairs of
+ * energies_out, split into W_k and E_k by the caller. */
+
+/* Sec. II.A: the time average over the steps k >= n_eq (0-based),
+ *   out[0] = E_bar = sum W_k E_k / sum W_k,
+ *   out[1] = sigma_E^2 = (sum W_k E_k^2 / sum W_k) - E_bar^2 (the squared
+ *            energies take the same weights),
+ *   out[2] = the number N of those steps.
+ * E_bar and sigma_E^2 are NaN when N = 0 or sum W_k = 0.  EINVAL on null
+ * pointers or negative sizes. */
+afq_status afq_stats_time_average(const double* w, const double* e, int64_t n, int64_t n_eq,
+                                  double* out);
+
+/* The correlation length kappa of Eq. (variance), sigma_Ebar^2 =
+ * sigma_E^2 kappa / N, from the unweighted series e[0..n):
+ *   out[0] = 1 + 2 sum_{t=1}^{M} rho(t), rho(t) = C(t) / C(0) with
+ *            C(t) = sum_i (E_i - m)(E_{i+t} - m) / (n - t), and the window
+ *            M the smallest with M >= c kappa(M) (Sokal; c = 5 is usual),
+ *   out[1] = M,
+ *   out[2] = (se_l / se_0)^2 from the blocking transformation (block means
+ *            of 2^l samples) at the smallest level l with
+ *            (2^l)^3 > 2 n (se_l / se_0)^4 (Lee, Needs, Drummond, Towler),
+ *   out[3] = l.
+ * EINVAL for n < 2, c <= 0 or a non-finite entry. */
+afq_status afq_stats_kappa(const double* e, int64_t n, double c, double* out);
+
+/* The blocking levels behind out[2] above: for l < min(*n_levels,
+ * max_levels), levels[3 l + 0..2] = (n_l, se_l, se_l / sqrt(2 (n_l - 1)))
+ * with se_l^2 = sum (x - x_bar)^2 / (n_l (n_l - 1)) over the n_l block
+ * means (a trailing odd sample dropped at each halving).  *n_levels gets
+ * the number of levels with n_l >= 2. */
+afq_status afq_stats_blocking(const double* e, int64_t n, double* levels, int32_t max_levels,
+                              int32_t* n_levels);
+
+/* Time-step extrapolation (Sec. V.G): least squares (weights 1 / sigma_i^2,
+ * or 1 when sigma is NULL) of E(tau_i) = E0 + alpha tau + beta tau^2
+ * (Eq. square_fit; AFQ_FIT_QUADRATIC), E0 + beta tau^2 (Eq.
+ * pure_square_fit; AFQ_FIT_PURE_SQUARE) or E0 + alpha tau (AFQ_FIT_LINEAR).
+ * coef[3] = (E0, alpha, beta) with the absent term 0; err[0] = the standard
+ * error of E0 from (A^T Sigma^-1 A)^-1, err[1] = sigma_x = sqrt(sum
+ * sigma_i^2) / n (Eq. staterr; NaN when sigma is NULL).  EINVAL for fewer
+ * points than terms or a non-positive sigma, ENUMERIC for a singular
+ * system (repeated tau). */
+enum { AFQ_FIT_QUADRATIC = 0, AFQ_FIT_PURE_SQUARE = 1, AFQ_FIT_LINEAR = 2 };
+afq_status afq_tau_fit(const double* tau, const double* e, const double* sigma, int32_t n,
+                       int32_t form, double* coef, double* err);
+
 #ifdef __cplusplus
 }
 #endif

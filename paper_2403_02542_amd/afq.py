@@ -28,8 +28,10 @@ EXPORTED = (
     "afq_local_energy_adjoint", "afq_force_bias_adjoint", "afq_get_walkers",
     "afq_set_walkers", "afq_fill_fields", "afq_get_counters", "afq_profile",
     "afq_profile_read", "afq_sync", "afq_autotune", "afq_get_e0",
-    "afq_local_energy_batch_noalloc",
+    "afq_local_energy_batch_noalloc", "afq_stats_time_average", "afq_stats_kappa",
+    "afq_stats_blocking", "afq_tau_fit",
 )
+FIT_QUADRATIC, FIT_PURE_SQUARE, FIT_LINEAR = 0, 1, 2
 PHASES = ("fields", "force_bias", "opbuild", "onebody", "exponential", "overlap", "weight", "qr",
           "exchange", "energy", "coulomb", "pop_control")
 
@@ -88,6 +90,10 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "afq_profile_read": (i32, [P, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.c_int]),
         "afq_sync": (i32, [P]),
         "afq_autotune": (i32, [P, ctypes.POINTER(i32), i32, i32]),
+        "afq_stats_time_average": (i32, [P, P, i64, i64, ctypes.POINTER(d)]),
+        "afq_stats_kappa": (i32, [P, i64, d, ctypes.POINTER(d)]),
+        "afq_stats_blocking": (i32, [P, i64, ctypes.POINTER(d), i32, ctypes.POINTER(i32)]),
+        "afq_tau_fit": (i32, [P, P, P, i32, i32, ctypes.POINTER(d), ctypes.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -123,6 +129,54 @@ def _arg(x, dtype):
         return x.data_ptr(), int(x.is_cuda), x
     a = np.ascontiguousarray(x, dtype=dtype)
     return a.ctypes.data, 0, a
+
+
+def _stat_check(code):
+    if code != OK:
+        raise AfqError(code, "invalid statistics input")
+
+
+def stats_time_average(w, e, n_eq=0):
+    """(E_bar, sigma_E^2, N) of afq_stats_time_average."""
+    wa = np.ascontiguousarray(w, dtype=np.float64)
+    ea = np.ascontiguousarray(e, dtype=np.float64)
+    if wa.shape != ea.shape:
+        raise ValueError("w and e differ in length")
+    out = (ctypes.c_double * 3)()
+    _stat_check(lib().afq_stats_time_average(wa.ctypes.data, ea.ctypes.data, len(ea), int(n_eq),
+                                             out))
+    return out[0], out[1], int(out[2])
+
+
+def stats_kappa(e, c=5.0):
+    """dict(acf=kappa, window=M, block=kappa, level=l) of afq_stats_kappa."""
+    ea = np.ascontiguousarray(e, dtype=np.float64)
+    out = (ctypes.c_double * 4)()
+    _stat_check(lib().afq_stats_kappa(ea.ctypes.data, len(ea), float(c), out))
+    return {"acf": out[0], "window": int(out[1]), "block": out[2], "level": int(out[3])}
+
+
+def stats_blocking(e):
+    """[(n_l, se_l, se_err_l)] of afq_stats_blocking."""
+    ea = np.ascontiguousarray(e, dtype=np.float64)
+    cap = 64
+    buf = (ctypes.c_double * (3 * cap))()
+    nl = ctypes.c_int32()
+    _stat_check(lib().afq_stats_blocking(ea.ctypes.data, len(ea), buf, cap, ctypes.byref(nl)))
+    return [(int(buf[3 * l]), buf[3 * l + 1], buf[3 * l + 2]) for l in range(min(nl.value, cap))]
+
+
+def tau_fit(tau, e, sigma=None, form=FIT_QUADRATIC):
+    """((E0, alpha, beta), err_E0, sigma_x) of afq_tau_fit."""
+    ta = np.ascontiguousarray(tau, dtype=np.float64)
+    ea = np.ascontiguousarray(e, dtype=np.float64)
+    sa = None if sigma is None else np.ascontiguousarray(sigma, dtype=np.float64)
+    coef = (ctypes.c_double * 3)()
+    err = (ctypes.c_double * 2)()
+    _stat_check(lib().afq_tau_fit(ta.ctypes.data, ea.ctypes.data,
+                                  None if sa is None else sa.ctypes.data, len(ta), int(form),
+                                  coef, err))
+    return (coef[0], coef[1], coef[2]), err[0], err[1]
 
 
 class Context:
