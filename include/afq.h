@@ -139,7 +139,18 @@ typedef struct {
                             Philox4x64-10 key (seed, sys_id + 2^32), counter
                             t + 1, word 0, u = (x >> 11) 2^-53; every copy gets
                             weight 1; T = 0 leaves the walkers alone             */
+  int32_t propagator;    /* AFQ_PROP_*: the orbital update of a step (Sec. III);
+                            SPLIT1 and TAYLOR need precision FP64 or MIXED_ENERGY */
 } afq_prop_params;
+
+/* Propagators (Sec. III), with A = -tau H_int^w and H1 the effective
+ * one-body matrix (h - 1/2 sum_g L_g L_g + sum_g Lbar_g L_g):
+ *  SPLIT2: exp(-tau H1 / 2) exp(A) exp(-tau H1 / 2) Phi (Sec. III.B),
+ *  SPLIT1: exp(-tau H1) exp(A) Phi (Sec. III.A),
+ *  TAYLOR: exp(A - tau H1) Phi, the refactorised exp(-tau H_eff^w) of
+ *          Sec. III.C, by the step's exponential method (exp_method).
+ * exp(-tau H1) and exp(-tau H1 / 2) are exact (eigendecomposition). */
+enum { AFQ_PROP_SPLIT2 = 0, AFQ_PROP_SPLIT1 = 1, AFQ_PROP_TAYLOR = 2 };
 
 /* Schedules of afq_propagate_batch.
  *  SERIAL:  system after system, phase after phase, on the context stream.

@@ -407,13 +407,41 @@ def init_walker(p: Prepared, phi0=None) -> Walker:
     return Walker(phi, logdet, theta, 1.0, theta is not None)
 
 
+PROP_SPLIT2, PROP_SPLIT1, PROP_TAYLOR = 0, 1, 2
+
+
+def full_step_propagator(H1: np.ndarray, tau: float) -> np.ndarray:
+    """exp(-tau H1), exactly by diagonalisation (Split-1, Sec. III.A)."""
+    e, v = np.linalg.eigh(H1)
+    return (v * np.exp(-tau * e)) @ v.T
+
+
+def propagate_orbitals(p: Prepared, phi: np.ndarray, A: np.ndarray, method: int, k: int,
+                       prop: int = PROP_SPLIT2) -> np.ndarray:
+    """The orbital update of one step with A = -tau H_int^w (Sec. III):
+      Split-2 (Sec. III.B): exp(-tau H1/2) exp(A) exp(-tau H1/2) Phi,
+      Split-1 (Sec. III.A): exp(-tau H1) exp(A) Phi (the interaction acts
+        first: it is the right factor of the split product),
+      Taylor propagator (Sec. III.C): exp(A - tau H1) Phi, the refactorised
+        exp(-tau H_eff^w), with the exponential method of the step.
+    H1 is the effective one-body matrix of `effective_one_body`."""
+    if prop == PROP_SPLIT2:
+        return p.B @ exponential(A, p.B @ phi, method, k)
+    if prop == PROP_SPLIT1:
+        return full_step_propagator(p.H1, p.tau) @ exponential(A, phi, method, k)
+    if prop == PROP_TAYLOR:
+        return exponential(A - p.tau * p.H1, phi, method, k)
+    raise ValueError(f"unknown propagator {prop}")
+
+
 def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
-                reorth: bool):
-    """One Split-2 step of one walker: returns (new walker, StepInfo).
+                reorth: bool, prop: int = PROP_SPLIT2):
+    """One step of one walker (Split-2 unless `prop` says otherwise):
+    returns (new walker, StepInfo).
 
     Order: force bias at the start-of-step Green's function (Reading: the
-    paper does not say where f is evaluated), operator, exp(-tau H1/2),
-    exponential of A, exp(-tau H1/2), overlap and weight, optional
+    paper does not say where f is evaluated), operator, the orbital update
+    of `propagate_orbitals`, overlap and weight, optional
     reorthonormalisation, local energy of the new determinant."""
     if not wk.alive:
         e = local_energy(p, wk.phi, wk.theta)
@@ -422,9 +450,7 @@ def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
     ell = coulomb_vector(p, wk.theta)
     f, fbar = force_bias(p, ell)
     A, s_mf, log_i = interaction_operator(p, x, fbar)
-    phi = p.B @ wk.phi
-    phi = exponential(A, phi, method, k)
-    phi = p.B @ phi
+    phi = propagate_orbitals(p, wk.phi, A, method, k, prop)
     logdet, theta = overlap(p.psi_t, phi)
     if theta is None or not np.all(np.isfinite(theta)) or not np.isfinite(logdet):
         dead = Walker(wk.phi, wk.logdet, wk.theta, 0.0, False)
@@ -457,7 +483,7 @@ def reorth_due(step: int, every: int) -> bool:
 
 def run(p: Prepared, walkers, fields_of_step, n_steps: int, method: int,
         k: int, reorth_every: int, step0: int = 0, e0_state: E0State = None,
-        pop_every: int = 0, comb_u=None):
+        pop_every: int = 0, comb_u=None, prop: int = PROP_SPLIT2):
     """Propagate a list of walkers; fields_of_step(t) -> (W, G) array.
 
     Returns (walkers, history) where history[s] holds per-walker arrays of
@@ -474,7 +500,7 @@ def run(p: Prepared, walkers, fields_of_step, n_steps: int, method: int,
         infos = []
         new = []
         for w, wk in enumerate(walkers):
-            nw, info = walker_step(p, wk, x[w], method, k, reorth_due(t, reorth_every))
+            nw, info = walker_step(p, wk, x[w], method, k, reorth_due(t, reorth_every), prop)
             new.append(nw)
             infos.append(info)
         walkers = new

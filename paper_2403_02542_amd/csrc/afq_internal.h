@@ -43,6 +43,7 @@ struct SysDev {
   double* H1 = nullptr;       // [M][M]
   double* Bhalf = nullptr;    // [M][M] exp(-tau H1 / 2)
   double* Bm1 = nullptr;      // [M][M] exp(-tau H1 / 2) - I (expm1 form)
+  double* Bfull = nullptr;    // [M][M] exp(-tau H1) (Split-1)
   double tau_b = -1.0;
   double e_const = 0.0, e_trial = 0.0;
   std::vector<double> h1_evals, h1_evecs;   // host eigendecomposition of H1
@@ -259,6 +260,13 @@ hipError_t launch_split_lt(SysDev& s, hipStream_t st);
 // BF16-split operator build: pieces of the field coefficients, then the
 // operator pieces s.Ab straight from the piece products.
 hipError_t launch_opbuild_mx(SysDev& s, hipStream_t st);
+// out = Bm in (FP64) for a given symmetric M x M matrix (Split-1's exp(-tau H1)).
+hipError_t launch_onebody_mat(SysDev& s, const double* Bm, const double* in_re,
+                              const double* in_im, double* out_re, double* out_im,
+                              hipStream_t st);
+// A^w += alpha D (real plane) for every walker: the refactorised operator
+// A - tau H1 with D = H1, alpha = -tau.
+hipError_t launch_add_real(SysDev& s, const double* D, double alpha, hipStream_t st);
 hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                           double* out_im, hipStream_t st);
 // Krylov exponential of the operator on every orbital: out = krylov_k(A, in);

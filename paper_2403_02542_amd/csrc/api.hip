@@ -188,27 +188,33 @@ afq_status check_symmetric(afq_ctx* ctx, const double* X, int64_t nb, int n, con
 afq_status ensure_half_step(afq_ctx* ctx, SysDev& s, double tau) {
   if (s.tau_b == tau && s.Bhalf && s.Bm1) return AFQ_OK;
   const int M = s.M;
-  std::vector<double> d(M), dm(M), B((size_t)M * M, 0.0), Bm((size_t)M * M, 0.0);
+  std::vector<double> d(M), dm(M), df(M), B((size_t)M * M, 0.0), Bm((size_t)M * M, 0.0),
+      Bf((size_t)M * M, 0.0);
   for (int k = 0; k < M; ++k) {
     d[k] = std::exp(-0.5 * tau * s.h1_evals[k]);
     dm[k] = std::expm1(-0.5 * tau * s.h1_evals[k]);
+    df[k] = std::exp(-tau * s.h1_evals[k]);
   }
   const double* V = s.h1_evecs.data();
   for (int p = 0; p < M; ++p)
     for (int q = p; q < M; ++q) {
-      double acc = 0.0, am = 0.0;
+      double acc = 0.0, am = 0.0, af = 0.0;
       for (int k = 0; k < M; ++k) {
         const double vv = V[(size_t)p * M + k] * V[(size_t)q * M + k];
         acc += vv * d[k];
         am += vv * dm[k];
+        af += vv * df[k];
       }
       B[(size_t)p * M + q] = acc;
       B[(size_t)q * M + p] = acc;
       Bm[(size_t)p * M + q] = am;
       Bm[(size_t)q * M + p] = am;
+      Bf[(size_t)p * M + q] = af;
+      Bf[(size_t)q * M + p] = af;
     }
   HIPCHK(hipMemcpy(s.Bhalf, B.data(), sizeof(double) * M * M, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(s.Bm1, Bm.data(), sizeof(double) * M * M, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s.Bfull, Bf.data(), sizeof(double) * M * M, hipMemcpyHostToDevice));
   s.tau_b = tau;
   return AFQ_OK;
 }
@@ -374,6 +380,22 @@ bool reorth_due(uint64_t t, int every) { return every > 0 && ((t + 1) % (uint64_
 // force bias, operator, B exp(A) B, overlap and weight, reorthonormalisation
 // and the commit of the new state.  With cs set (captured replays) the step
 // index is read on the device, offset by `add`.
+// out = exp(A) in by the step's method; t3 and `spare` (both W N M planes,
+// distinct from in and out) are scratch.
+afq_status exponential(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, const double* in_re,
+                       const double* in_im, double* out_re, double* out_im, double* spare_re,
+                       double* spare_im, hipStream_t st) {
+  if (P.exp_method == AFQ_EXP_KRYLOV)
+    HIPCHK(launch_krylov(s, P.exp_order, in_re, in_im, out_re, out_im, s.t3_re, s.t3_im, st));
+  else if (P.exp_method == AFQ_EXP_BLOCK_KRYLOV)
+    HIPCHK(launch_block_krylov(s, P.exp_order, in_re, in_im, out_re, out_im, s.t3_re, s.t3_im,
+                                 st));
+  else
+    HIPCHK(launch_taylor(s, P.exp_order, in_re, in_im, out_re, out_im, s.t3_re, s.t3_im,
+                           spare_re, spare_im, st));
+  return AFQ_OK;
+}
+
 afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_params& P,
                       const double* x_given, uint64_t t, const CallState* cs, int add,
                       hipStream_t st) {
@@ -392,24 +414,32 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
     Phase ph(ctx, AFQ_PH_OPBUILD);
     HIPCHK(launch_opbuild(s, st));
   }
-  {
+  if (P.propagator == AFQ_PROP_TAYLOR) {
+    // the refactorised operator A - tau H1, its exponential straight into
+    // the proposed orbitals (t1 as scratch)
+    Phase ph(ctx, AFQ_PH_EXPONENTIAL);
+    HIPCHK(launch_add_real(s, s.H1, -P.tau, st));
+    TRY(exponential(ctx, s, P, s.phi_re, s.phi_im, s.phn_re, s.phn_im, s.t1_re, s.t1_im, st));
+    return AFQ_OK;
+  }
+  const double* in_re = s.phi_re;
+  const double* in_im = s.phi_im;
+  if (P.propagator == AFQ_PROP_SPLIT2) {
     Phase ph(ctx, AFQ_PH_ONEBODY);
     HIPCHK(launch_onebody(s, s.phi_re, s.phi_im, s.t1_re, s.t1_im, st));
+    in_re = s.t1_re;
+    in_im = s.t1_im;
   }
   {
     Phase ph(ctx, AFQ_PH_EXPONENTIAL);
-    if (P.exp_method == AFQ_EXP_KRYLOV)
-      HIPCHK(launch_krylov(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re, s.t3_im, st));
-    else if (P.exp_method == AFQ_EXP_BLOCK_KRYLOV)
-      HIPCHK(launch_block_krylov(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re,
-                                 s.t3_im, st));
-    else
-      HIPCHK(launch_taylor(s, P.exp_order, s.t1_re, s.t1_im, s.t2_re, s.t2_im, s.t3_re, s.t3_im,
-                           s.phn_re, s.phn_im, st));
+    TRY(exponential(ctx, s, P, in_re, in_im, s.t2_re, s.t2_im, s.phn_re, s.phn_im, st));
   }
   {
     Phase ph(ctx, AFQ_PH_ONEBODY);
-    HIPCHK(launch_onebody(s, s.t2_re, s.t2_im, s.phn_re, s.phn_im, st));
+    if (P.propagator == AFQ_PROP_SPLIT2)
+      HIPCHK(launch_onebody(s, s.t2_re, s.t2_im, s.phn_re, s.phn_im, st));
+    else
+      HIPCHK(launch_onebody_mat(s, s.Bfull, s.t2_re, s.t2_im, s.phn_re, s.phn_im, st));
   }
   return AFQ_OK;
 }
@@ -797,6 +827,7 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
   put_bytes(key, P.seed);
   put_bytes(key, P.e0_window);
   put_bytes(key, P.pop_every);
+  put_bytes(key, P.propagator);
   afq_ctx::GraphEntry* ge = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) ge = &g;
@@ -1015,6 +1046,7 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
   TRY(dalloc(ctx, own, &s.H1, MM));
   TRY(dalloc(ctx, own, &s.Bhalf, MM));
   TRY(dalloc(ctx, own, &s.Bm1, MM));
+  TRY(dalloc(ctx, own, &s.Bfull, MM));
   HIPCHK(hipMemcpy(s.psit, pt.data(), pt.size() * 8, hipMemcpyHostToDevice));
   // Psi_T^T L_g for every g, and Psi_T^T h in the last block
   GemmArgs g{};
@@ -1220,6 +1252,11 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   if (P->e0_window < 0 || P->e0_window > kE0Max)
     return fail(ctx, AFQ_EINVAL, "e0_window must be in [0, 64]");
   if (P->pop_every < 0) return fail(ctx, AFQ_EINVAL, "pop_every < 0");
+  if (P->propagator < AFQ_PROP_SPLIT2 || P->propagator > AFQ_PROP_TAYLOR)
+    return fail(ctx, AFQ_EINVAL, "unknown propagator");
+  if (P->propagator != AFQ_PROP_SPLIT2 && op_pieces_of(P->precision) > 0)
+    return fail(ctx, AFQ_EINVAL, "Split-1 and the refactorised propagator run with FP64 "
+                                 "propagation (precision FP64 or MIXED_ENERGY)");
   if (P->schedule < AFQ_SCHED_AUTO || P->schedule > AFQ_SCHED_GRAPH)
     return fail(ctx, AFQ_EINVAL, "unknown schedule");
   const bool batch_ok = !P->fields && P->energy_every <= 1 && !ctx->profiling;

@@ -588,7 +588,7 @@ namespace {
 
 template <int PC>
 hipError_t onebody_p(SysDev& s, const double* in_re, const double* in_im, double* out_re,
-                     double* out_im, hipStream_t st) {
+                     double* out_im, hipStream_t st, const double* Bmat = nullptr) {
   constexpr size_t lds = pipe_lds_bytes<4, 2, 2, 5, PC>();
   static bool lds_ok = false;
   if (!lds_ok) {
@@ -601,7 +601,7 @@ hipError_t onebody_p(SysDev& s, const double* in_re, const double* in_im, double
   const int nrt = (2 * WN + OBP::ROWS - 1) / OBP::ROWS;
   const int nct = (s.M + OBP::COLS - 1) / OBP::COLS;
   hipLaunchKernelGGL(k_onebody<PC>, dim3(nrt * nct), dim3(OBP::NT), lds, st, WN, s.M, nct, in_re,
-                     in_im, PC ? s.Bm1 : s.Bhalf, out_re, out_im);
+                     in_im, Bmat ? Bmat : PC ? s.Bm1 : s.Bhalf, out_re, out_im);
   return hipGetLastError();
 }
 
@@ -624,6 +624,27 @@ hipError_t opbuild_fp64(SysDev& s, hipStream_t st) {
 }
 
 }  // namespace
+
+__global__ void k_add_real(int64_t MM, int W, const double* __restrict__ D, double alpha,
+                           double* __restrict__ A) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MM * W;
+       e += (int64_t)gridDim.x * blockDim.x)
+    A[e] = fma(alpha, D[e % MM], A[e]);
+}
+
+hipError_t launch_add_real(SysDev& s, const double* D, double alpha, hipStream_t st) {
+  const int64_t MM = (int64_t)s.M * s.M, n = MM * s.W;
+  const int64_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_add_real, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, st, MM,
+                     s.W, D, alpha, s.A_re);
+  return hipGetLastError();
+}
+
+hipError_t launch_onebody_mat(SysDev& s, const double* Bm, const double* in_re,
+                              const double* in_im, double* out_re, double* out_im,
+                              hipStream_t st) {
+  return onebody_p<0>(s, in_re, in_im, out_re, out_im, st, Bm);
+}
 
 hipError_t launch_onebody(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                           double* out_im, hipStream_t st) {

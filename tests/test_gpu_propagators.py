@@ -1,0 +1,129 @@
+"""GPU parity of the propagator variants (Sec. III: Split-1 and the
+refactorised Taylor propagator beside Split-2) against the oracle, and the
+size consistency of Sec. V.F on a direct sum of two systems, through the
+C ABI."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import afq_workloads as W
+import gpu_common as C
+from oracle import afq_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    C.require_gpu()
+    from paper_2403_02542_amd import afq
+    c = afq.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("prop,method", [(O.PROP_SPLIT1, O.EXP_KRYLOV),
+                                         (O.PROP_TAYLOR, O.EXP_TAYLOR),
+                                         (O.PROP_TAYLOR, O.EXP_KRYLOV),
+                                         (O.PROP_SPLIT1, O.EXP_BLOCK_KRYLOV)])
+def test_propagators_c1_all_walkers(ctx, prop, method):
+    """c1 in full (16 walkers, 20 steps), k = 6 (block order 4)."""
+    cfg = W.CONFIGS["c1"]
+    case = C.Case.from_config("c1")
+    k = 4 if method == O.EXP_BLOCK_KRYLOV else cfg.k
+    worst, flagged, _ = C.run_pair(case, ctx, tau=cfg.tau, k=k, method=method,
+                                   reorth=cfg.reorth_every, n_steps=cfg.steps, n_walkers=cfg.W,
+                                   track=list(range(cfg.W)), prop=prop)
+    print("c1 propagator", prop, "method", method, worst, "flagged", sorted(flagged))
+    assert len(flagged) <= 2
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+@pytest.mark.parametrize("prop", [O.PROP_SPLIT1, O.PROP_TAYLOR])
+def test_propagators_c2_subset(ctx, prop):
+    """c2 (256 walkers, Krylov 8), 3 walkers tracked over 12 steps."""
+    cfg = W.CONFIGS["c2"]
+    case = C.Case.from_config("c2")
+    worst, flagged, _ = C.run_pair(case, ctx, tau=cfg.tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                   reorth=cfg.reorth_every, n_steps=12, n_walkers=cfg.W,
+                                   track=[0, 128, 255], prop=prop)
+    print("c2 propagator", prop, worst, "flagged", sorted(flagged))
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+def test_propagator_arguments(ctx):
+    from paper_2403_02542_amd import afq
+    case = C.Case.from_config("c1")
+    sid = case.gpu(ctx, 4)
+    with pytest.raises(afq.AfqError) as e:
+        ctx.propagate_batch(sid, tau=0.01, n_steps=1, propagator=3)
+    assert e.value.code == afq.EINVAL
+    with pytest.raises(afq.AfqError) as e:
+        ctx.propagate_batch(sid, tau=0.01, n_steps=1, propagator=afq.PROP_SPLIT1,
+                            precision=afq.PREC_MIXED)
+    assert e.value.code == afq.EINVAL
+    ctx.propagate_batch(sid, tau=0.01, n_steps=1, propagator=afq.PROP_TAYLOR,
+                        precision=afq.PREC_MIXED_ENERGY)
+
+
+def _sub(M, N, G, seed):
+    ham = W.hamiltonian(M, G, 0.1, 0.3 / np.sqrt(M), seed, 0.0)
+    return ham.h, ham.L, W.rhf_trial(ham.h, ham.L, N, n_iter=3)
+
+
+@pytest.mark.parametrize("prop", [O.PROP_SPLIT2, O.PROP_SPLIT1, O.PROP_TAYLOR])
+def test_size_consistency_direct_sum(ctx, prop):
+    """Sec. V.F on a synthetic pair (M = 24 + 20, N = 5 + 4, G = 60 + 50):
+    the system A + B (block-diagonal h, Cholesky vectors of A then of B,
+    block-diagonal trial) propagated with the fields (x_A, x_B) keeps every
+    walker the direct sum of the walkers of A and B, and log <Psi_T|Phi>
+    and E_L add, to the FP64 parity bar, over 10 steps with QR every 2.
+    The weights do not factorise (the phaseless cosine takes the summed
+    phase), so the size-consistency error of the estimator,
+    E_s = E_AB - E_A - E_B, is only reported."""
+    import torch
+    (ha, La, pa), (hb, Lb, pb) = _sub(24, 5, 60, 31), _sub(20, 4, 50, 32)
+    Ma, Mb, Ga, Gb = 24, 20, 60, 50
+    h = scipy.linalg.block_diag(ha, hb)
+    L = np.zeros((Ga + Gb, Ma + Mb, Ma + Mb))
+    L[:Ga, :Ma, :Ma] = La
+    L[Ga:, Ma:, Ma:] = Lb
+    psi = scipy.linalg.block_diag(pa, pb)
+    nw, tau, steps = 64, 0.05, 10
+    ids = {}
+    for name, (hh, LL, pp) in {"A": (ha, La, pa), "B": (hb, Lb, pb), "AB": (h, L, psi)}.items():
+        sid = ctx.init_hamiltonian(hh, LL, 0.0)
+        ctx.init_trial(sid, pp)
+        ctx.init_walkers(sid, nw)
+        ids[name] = sid
+    en = {n: torch.zeros((1, steps, 2), dtype=torch.float64, device="cuda") for n in ids}
+    rng = np.random.default_rng(9)
+    for s in range(steps):
+        xa = rng.standard_normal((nw, Ga))
+        xb = rng.standard_normal((nw, Gb))
+        xs = {"A": xa, "B": xb, "AB": np.concatenate([xa, xb], axis=1)}
+        for n, sid in ids.items():
+            ctx.propagate_batch(sid, tau=tau, n_steps=1, exp_method=O.EXP_KRYLOV, exp_order=6,
+                                reorth_every=2, step0=s, fields=C.to_dev(xs[n]),
+                                energies_out=en[n][:, s:s + 1], propagator=prop)
+    torch.cuda.synchronize()
+    st = {n: ctx.get_walkers(sid) for n, sid in ids.items()}
+    el = {n: ctx.local_energy_batch(sid) for n, sid in ids.items()}
+    worst_phi = worst_ld = worst_el = 0.0
+    for w in range(nw):
+        if not (st["A"]["alive"][w] and st["B"]["alive"][w] and st["AB"]["alive"][w]):
+            continue
+        blk = scipy.linalg.block_diag(st["A"]["phi"][w], st["B"]["phi"][w])
+        worst_phi = max(worst_phi, C.rel(st["AB"]["phi"][w], blk))
+        ld = st["A"]["log_ovlp"][w].real + st["B"]["log_ovlp"][w].real
+        worst_ld = max(worst_ld, abs(st["AB"]["log_ovlp"][w].real - ld) / max(1.0, abs(ld)))
+        e = el["A"][w] + el["B"][w]
+        worst_el = max(worst_el, abs(el["AB"][w] - e) / max(1.0, abs(e)))
+    e = {n: en[n].cpu().numpy()[0] for n in ids}
+    ek = {n: np.where(e[n][:, 1] > 0, e[n][:, 0] / np.maximum(e[n][:, 1], 1e-300), np.nan)
+          for n in ids}
+    print(f"propagator {prop}: phi {worst_phi:.2e}, log overlap {worst_ld:.2e}, E_L {worst_el:.2e}; "
+          f"E_s per step (Ha) {np.round(ek['AB'] - ek['A'] - ek['B'], 5)}", flush=True)
+    assert worst_phi < C.RTOL and worst_ld < C.RTOL and worst_el < C.RTOL
