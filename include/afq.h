@@ -140,7 +140,7 @@ typedef struct {
                             t + 1, word 0, u = (x >> 11) 2^-53; every copy gets
                             weight 1; T = 0 leaves the walkers alone             */
   int32_t propagator;    /* AFQ_PROP_*: the orbital update of a step (Sec. III);
-                            SPLIT1 and TAYLOR need precision FP64 or MIXED_ENERGY */
+                            all but SPLIT2 need precision FP64 or MIXED_ENERGY  */
 } afq_prop_params;
 
 /* Propagators (Sec. III), with A = -tau H_int^w and H1 the effective
@@ -148,9 +148,12 @@ typedef struct {
  *  SPLIT2: exp(-tau H1 / 2) exp(A) exp(-tau H1 / 2) Phi (Sec. III.B),
  *  SPLIT1: exp(-tau H1) exp(A) Phi (Sec. III.A),
  *  TAYLOR: exp(A - tau H1) Phi, the refactorised exp(-tau H_eff^w) of
- *          Sec. III.C, by the step's exponential method (exp_method).
+ *          Sec. III.C, by the step's exponential method (exp_method),
+ *  CN:     (I - A_T / 2)^-1 (I + A_T / 2) Phi with A_T = A - tau H1, the
+ *          Crank-Nicolson form of Sec. III.D, by a dense solve per walker
+ *          (Gauss-Jordan with partial pivoting; exp_method is not used).
  * exp(-tau H1) and exp(-tau H1 / 2) are exact (eigendecomposition). */
-enum { AFQ_PROP_SPLIT2 = 0, AFQ_PROP_SPLIT1 = 1, AFQ_PROP_TAYLOR = 2 };
+enum { AFQ_PROP_SPLIT2 = 0, AFQ_PROP_SPLIT1 = 1, AFQ_PROP_TAYLOR = 2, AFQ_PROP_CN = 3 };
 
 /* Schedules of afq_propagate_batch.
  *  SERIAL:  system after system, phase after phase, on the context stream.

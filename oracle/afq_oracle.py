@@ -407,7 +407,7 @@ def init_walker(p: Prepared, phi0=None) -> Walker:
     return Walker(phi, logdet, theta, 1.0, theta is not None)
 
 
-PROP_SPLIT2, PROP_SPLIT1, PROP_TAYLOR = 0, 1, 2
+PROP_SPLIT2, PROP_SPLIT1, PROP_TAYLOR, PROP_CN = 0, 1, 2, 3
 
 
 def full_step_propagator(H1: np.ndarray, tau: float) -> np.ndarray:
@@ -423,7 +423,10 @@ def propagate_orbitals(p: Prepared, phi: np.ndarray, A: np.ndarray, method: int,
       Split-1 (Sec. III.A): exp(-tau H1) exp(A) Phi (the interaction acts
         first: it is the right factor of the split product),
       Taylor propagator (Sec. III.C): exp(A - tau H1) Phi, the refactorised
-        exp(-tau H_eff^w), with the exponential method of the step.
+        exp(-tau H_eff^w), with the exponential method of the step,
+      Crank-Nicolson (Sec. III.D): (1 + tau H_eff / 2)^-1 (1 - tau H_eff / 2)
+        Phi = (I - A_T / 2)^-1 (I + A_T / 2) Phi with A_T = A - tau H1, by a
+        dense solve (no exponential).
     H1 is the effective one-body matrix of `effective_one_body`."""
     if prop == PROP_SPLIT2:
         return p.B @ exponential(A, p.B @ phi, method, k)
@@ -431,6 +434,10 @@ def propagate_orbitals(p: Prepared, phi: np.ndarray, A: np.ndarray, method: int,
         return full_step_propagator(p.H1, p.tau) @ exponential(A, phi, method, k)
     if prop == PROP_TAYLOR:
         return exponential(A - p.tau * p.H1, phi, method, k)
+    if prop == PROP_CN:
+        At = A - p.tau * p.H1
+        eye = np.eye(p.M)
+        return np.linalg.solve(eye - 0.5 * At, phi + 0.5 * (At @ phi))
     raise ValueError(f"unknown propagator {prop}")
 
 

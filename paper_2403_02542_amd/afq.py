@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libafq.so"
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = range(6)
 EXP_KRYLOV, EXP_TAYLOR, EXP_BLOCK_KRYLOV = 0, 1, 2
-PROP_SPLIT2, PROP_SPLIT1, PROP_TAYLOR = 0, 1, 2
+PROP_SPLIT2, PROP_SPLIT1, PROP_TAYLOR, PROP_CN = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED, PREC_MIXED_FAST, PREC_MIXED_ENERGY = 0, 1, 2, 3
 SCHED_AUTO, SCHED_SERIAL, SCHED_STREAMS, SCHED_GRAPH = 0, 1, 2, 3
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENUMERIC"}

@@ -247,6 +247,14 @@ struct VecOut {
 hipError_t launch_opbuild(SysDev& s, hipStream_t st);
 // out = A v over all walkers (the operator-orbital product of the exponentials).
 hipError_t launch_matvec(SysDev& s, VecRef v, VecOut o, hipStream_t st);
+// o = scale A v and sum += o over all walkers.
+hipError_t launch_matvec_acc(SysDev& s, VecRef v, VecOut o, double scale, VecOut sum,
+                             hipStream_t st);
+// Crank-Nicolson step out = (I - A/2)^-1 (I + A/2) in with A the current
+// operator (destroyed); t: W N M scratch planes.
+hipError_t launch_crank_nicolson(SysDev& s, const double* in_re, const double* in_im,
+                                 double* out_re, double* out_im, double* t_re, double* t_im,
+                                 hipStream_t st);
 // Origins of the R x 16 blocks of an M x M symmetric matrix that hold an
 // element on or above the diagonal, row blocks outermost.
 void op_blocks(int M, int R, std::vector<int2>& out);

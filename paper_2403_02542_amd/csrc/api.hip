@@ -414,6 +414,12 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
     Phase ph(ctx, AFQ_PH_OPBUILD);
     HIPCHK(launch_opbuild(s, st));
   }
+  if (P.propagator == AFQ_PROP_CN) {
+    Phase ph(ctx, AFQ_PH_EXPONENTIAL);
+    HIPCHK(launch_add_real(s, s.H1, -P.tau, st));
+    HIPCHK(launch_crank_nicolson(s, s.phi_re, s.phi_im, s.phn_re, s.phn_im, s.t1_re, s.t1_im, st));
+    return AFQ_OK;
+  }
   if (P.propagator == AFQ_PROP_TAYLOR) {
     // the refactorised operator A - tau H1, its exponential straight into
     // the proposed orbitals (t1 as scratch)
@@ -1252,11 +1258,11 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   if (P->e0_window < 0 || P->e0_window > kE0Max)
     return fail(ctx, AFQ_EINVAL, "e0_window must be in [0, 64]");
   if (P->pop_every < 0) return fail(ctx, AFQ_EINVAL, "pop_every < 0");
-  if (P->propagator < AFQ_PROP_SPLIT2 || P->propagator > AFQ_PROP_TAYLOR)
+  if (P->propagator < AFQ_PROP_SPLIT2 || P->propagator > AFQ_PROP_CN)
     return fail(ctx, AFQ_EINVAL, "unknown propagator");
   if (P->propagator != AFQ_PROP_SPLIT2 && op_pieces_of(P->precision) > 0)
-    return fail(ctx, AFQ_EINVAL, "Split-1 and the refactorised propagator run with FP64 "
-                                 "propagation (precision FP64 or MIXED_ENERGY)");
+    return fail(ctx, AFQ_EINVAL, "Split-1, the refactorised and the Crank-Nicolson propagators "
+                                 "run with FP64 propagation (precision FP64 or MIXED_ENERGY)");
   if (P->schedule < AFQ_SCHED_AUTO || P->schedule > AFQ_SCHED_GRAPH)
     return fail(ctx, AFQ_EINVAL, "unknown schedule");
   const bool batch_ok = !P->fields && P->energy_every <= 1 && !ctx->profiling;

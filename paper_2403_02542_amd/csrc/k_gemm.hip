@@ -537,6 +537,11 @@ hipError_t launch_matvec(SysDev& s, VecRef v, VecOut o, hipStream_t st) {
   return run_matvec(s, v, o, 0, 1.0, o, st);
 }
 
+hipError_t launch_matvec_acc(SysDev& s, VecRef v, VecOut o, double scale, VecOut sum,
+                             hipStream_t st) {
+  return run_matvec(s, v, o, 1, scale, sum, st);
+}
+
 hipError_t launch_matvec_probe(SysDev& s, const double* in_re, const double* in_im, double* out_re,
                                double* out_im, hipStream_t st) {
   const int64_t sw = (int64_t)s.N * s.M;

@@ -1,5 +1,6 @@
-"""GPU parity of the propagator variants (Sec. III: Split-1 and the
-refactorised Taylor propagator beside Split-2) against the oracle, and the
+"""GPU parity of the propagator variants (Sec. III: Split-1, the
+refactorised Taylor propagator and Crank-Nicolson beside Split-2) against
+the oracle, and the
 size consistency of Sec. V.F on a direct sum of two systems, through the
 C ABI."""
 import numpy as np
@@ -25,7 +26,8 @@ def ctx():
 @pytest.mark.parametrize("prop,method", [(O.PROP_SPLIT1, O.EXP_KRYLOV),
                                          (O.PROP_TAYLOR, O.EXP_TAYLOR),
                                          (O.PROP_TAYLOR, O.EXP_KRYLOV),
-                                         (O.PROP_SPLIT1, O.EXP_BLOCK_KRYLOV)])
+                                         (O.PROP_SPLIT1, O.EXP_BLOCK_KRYLOV),
+                                         (O.PROP_CN, O.EXP_KRYLOV)])
 def test_propagators_c1_all_walkers(ctx, prop, method):
     """c1 in full (16 walkers, 20 steps), k = 6 (block order 4)."""
     cfg = W.CONFIGS["c1"]
@@ -40,7 +42,7 @@ def test_propagators_c1_all_walkers(ctx, prop, method):
         assert v < C.RTOL, (key, v)
 
 
-@pytest.mark.parametrize("prop", [O.PROP_SPLIT1, O.PROP_TAYLOR])
+@pytest.mark.parametrize("prop", [O.PROP_SPLIT1, O.PROP_TAYLOR, O.PROP_CN])
 def test_propagators_c2_subset(ctx, prop):
     """c2 (256 walkers, Krylov 8), 3 walkers tracked over 12 steps."""
     cfg = W.CONFIGS["c2"]
@@ -58,7 +60,7 @@ def test_propagator_arguments(ctx):
     case = C.Case.from_config("c1")
     sid = case.gpu(ctx, 4)
     with pytest.raises(afq.AfqError) as e:
-        ctx.propagate_batch(sid, tau=0.01, n_steps=1, propagator=3)
+        ctx.propagate_batch(sid, tau=0.01, n_steps=1, propagator=4)
     assert e.value.code == afq.EINVAL
     with pytest.raises(afq.AfqError) as e:
         ctx.propagate_batch(sid, tau=0.01, n_steps=1, propagator=afq.PROP_SPLIT1,
@@ -73,7 +75,7 @@ def _sub(M, N, G, seed):
     return ham.h, ham.L, W.rhf_trial(ham.h, ham.L, N, n_iter=3)
 
 
-@pytest.mark.parametrize("prop", [O.PROP_SPLIT2, O.PROP_SPLIT1, O.PROP_TAYLOR])
+@pytest.mark.parametrize("prop", [O.PROP_SPLIT2, O.PROP_SPLIT1, O.PROP_TAYLOR, O.PROP_CN])
 def test_size_consistency_direct_sum(ctx, prop):
     """Sec. V.F on a synthetic pair (M = 24 + 20, N = 5 + 4, G = 60 + 50):
     the system A + B (block-diagonal h, Cholesky vectors of A then of B,

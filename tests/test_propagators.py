@@ -1,6 +1,7 @@
-"""Oracle pins of the propagator variants (Sec. III): Split-1, Split-2 and
-the refactorised (Taylor) propagator, and of the size consistency of the
-local energy (Sec. V.F) on a direct sum of two systems.  CPU only."""
+"""Oracle pins of the propagator variants (Sec. III): Split-1, Split-2, the
+refactorised (Taylor) propagator and Crank-Nicolson, and of the size
+consistency of the local energy (Sec. V.F) on a direct sum of two systems.
+CPU only."""
 import math
 
 import numpy as np
@@ -10,7 +11,7 @@ import scipy.linalg
 import afq_workloads as W
 from oracle import afq_oracle as O
 
-PROPS = (O.PROP_SPLIT2, O.PROP_SPLIT1, O.PROP_TAYLOR)
+PROPS = (O.PROP_SPLIT2, O.PROP_SPLIT1, O.PROP_TAYLOR, O.PROP_CN)
 
 
 def _system(M, N, G, seed, diag=False, scale=0.3):
@@ -60,7 +61,7 @@ def test_commuting_operators_all_propagators_agree():
     _, fbar = O.force_bias(p, ell)
     A, _, _ = O.interaction_operator(p, x, fbar)
     phi = psi.astype(complex)
-    outs = [O.propagate_orbitals(p, phi, A, O.EXP_TAYLOR, 40, prop) for prop in PROPS]
+    outs = [O.propagate_orbitals(p, phi, A, O.EXP_TAYLOR, 40, prop) for prop in PROPS[:3]]
     want = _exact(A - p.tau * p.H1, phi)
     for o in outs:
         assert np.abs(o - want).max() < 1e-13
@@ -134,3 +135,36 @@ def test_size_consistency_of_one_walker(prop):
         assert abs(wab.logdet.real - (wa.logdet.real + wb.logdet.real)) < 1e-11
         blk = scipy.linalg.block_diag(wa.phi, wb.phi)
         assert np.abs(wab.phi - blk).max() < 1e-12
+
+
+def test_crank_nicolson_is_the_cayley_transform():
+    """Without interaction (L = 0), CN multiplies each eigenvector of H1 by
+    (1 - tau lambda / 2) / (1 + tau lambda / 2): checked against that
+    spectral form (eigh), not against a solve."""
+    M, N = 11, 3
+    h, _, psi = _system(M, N, 4, seed=6)
+    p = O.prepare(h, np.zeros((1, M, M)), 0.0, psi, tau=0.2)
+    lam, v = np.linalg.eigh(p.H1)
+    cay = (v * ((1.0 - 0.5 * p.tau * lam) / (1.0 + 0.5 * p.tau * lam))) @ v.T
+    phi = psi.astype(complex) * (1.0 + 0.5j)
+    got = O.propagate_orbitals(p, phi, np.zeros((M, M), complex), O.EXP_TAYLOR, 1, O.PROP_CN)
+    assert np.abs(got - cay @ phi).max() < 1e-13
+
+
+def test_crank_nicolson_error_scaling():
+    """CN is the (1,1) Pade approximant of exp(A_T): its one-step error
+    against exp(A_T) is A_T^3 / 12 + ..., O(tau^1.5) with A ~ sqrt(tau):
+    quartering tau divides it by ~8."""
+    M, N, G = 14, 3, 8
+    h, L, psi = _system(M, N, G, seed=7, scale=1.0)
+    x = np.random.default_rng(3).standard_normal(G)
+    diffs = []
+    for tau in (0.04, 0.01, 0.0025):
+        p = O.prepare(h, L, 0.0, psi, tau=tau)
+        A, _, _ = O.interaction_operator(p, x, np.zeros(G, complex))
+        phi = psi.astype(complex)
+        a = O.propagate_orbitals(p, phi, A, O.EXP_TAYLOR, 40, O.PROP_CN)
+        b = O.propagate_orbitals(p, phi, A, O.EXP_TAYLOR, 40, O.PROP_TAYLOR)
+        diffs.append(np.abs(a - b).max())
+    print(diffs, diffs[0] / diffs[1], diffs[1] / diffs[2])
+    assert diffs[1] / diffs[2] == pytest.approx(8.0, rel=0.15)
