@@ -50,7 +50,11 @@ enum {
  * (Sec. IV.D, Eq. bkrylov: one kN-dimensional Krylov space per walker for
  * all N orbitals, k N <= M; its small exponential needs one host
  * synchronisation per step, so the graph schedule does not run it). */
-enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1, AFQ_EXP_BLOCK_KRYLOV = 2 };
+enum { AFQ_EXP_KRYLOV = 0, AFQ_EXP_TAYLOR = 1, AFQ_EXP_BLOCK_KRYLOV = 2, AFQ_EXP_CHEBYSHEV = 3 };
+/* AFQ_EXP_CHEBYSHEV (Sec. IV.B, Eq. chebpoly): sum_{n=0}^{k} c_n T_n(A) Phi
+ * with the three-term recurrence T_n = 2 A T_{n-1} - T_{n-2} applied to A
+ * as it stands (no spectral shift or scaling), c_0 = J_0(i) = I_0(1),
+ * c_n = 2 i^n J_n(-i) = 2 I_n(1); k operator applications. */
 /* Precision of the dense contractions: FP64, or BF16-split operands on the
  * BF16 matrix cores with FP32 accumulation, three pieces per value (six
  * piece products, ~24 significand bits) or two pieces (three products, ~16

@@ -279,6 +279,37 @@ def block_krylov(A: np.ndarray, phi: np.ndarray, k: int) -> np.ndarray:
 
 
 EXP_BLOCK_KRYLOV = 2
+EXP_CHEBYSHEV = 3
+# The reference of the exponential comparisons (Sec. IV.E): the dense
+# exp(A) (scipy's expm), k unused.
+EXP_EXACT = -1
+
+
+def chebyshev_coefficient(n: int) -> float:
+    """c_0 = J_0(i), c_n = 2 i^n J_n(-i) for n > 0 (Sec. IV.B), evaluated as
+    printed with the Bessel function of complex argument; the imaginary
+    part vanishes (to rounding) and is dropped."""
+    import scipy.special
+    c = scipy.special.jv(0, 1j) if n == 0 else 2.0 * (1j ** n) * scipy.special.jv(n, -1j)
+    assert abs(c.imag) <= 1e-15 * max(1.0, abs(c.real))
+    return float(c.real)
+
+
+def chebyshev(A: np.ndarray, phi: np.ndarray, k: int) -> np.ndarray:
+    """cheb_k{A, Psi} = sum_{n=0..k} c_n T_n(A) Psi with T_0 = 1, T_1 = x,
+    T_n = 2 x T_{n-1} - T_{n-2} (Eq. chebpoly).  Reading: the expansion is
+    applied to A as it stands (the paper gives no spectral shift or scaling)."""
+    t_prev = phi.copy()
+    out = chebyshev_coefficient(0) * t_prev
+    if k == 0:
+        return out
+    t_cur = A @ phi
+    out = out + chebyshev_coefficient(1) * t_cur
+    for n in range(2, k + 1):
+        t_next = 2.0 * (A @ t_cur) - t_prev
+        out = out + chebyshev_coefficient(n) * t_next
+        t_prev, t_cur = t_cur, t_next
+    return out
 
 
 def exponential(A, phi, method: int, k: int):
@@ -288,6 +319,10 @@ def exponential(A, phi, method: int, k: int):
         return taylor(A, phi, k)
     if method == EXP_BLOCK_KRYLOV:
         return block_krylov(A, phi, k)
+    if method == EXP_CHEBYSHEV:
+        return chebyshev(A, phi, k)
+    if method == EXP_EXACT:
+        return scipy.linalg.expm(A) @ phi
     raise ValueError(f"unknown exponential method {method}")
 
 

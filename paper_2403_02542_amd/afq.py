@@ -17,7 +17,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libafq.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = range(6)
-EXP_KRYLOV, EXP_TAYLOR, EXP_BLOCK_KRYLOV = 0, 1, 2
+EXP_KRYLOV, EXP_TAYLOR, EXP_BLOCK_KRYLOV, EXP_CHEBYSHEV = 0, 1, 2, 3
 PROP_SPLIT2, PROP_SPLIT1, PROP_TAYLOR, PROP_CN = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED, PREC_MIXED_FAST, PREC_MIXED_ENERGY = 0, 1, 2, 3
 SCHED_AUTO, SCHED_SERIAL, SCHED_STREAMS, SCHED_GRAPH = 0, 1, 2, 3

@@ -250,6 +250,10 @@ hipError_t launch_matvec(SysDev& s, VecRef v, VecOut o, hipStream_t st);
 // o = scale A v and sum += o over all walkers.
 hipError_t launch_matvec_acc(SysDev& s, VecRef v, VecOut o, double scale, VecOut sum,
                              hipStream_t st);
+// Chebyshev expansion out = sum_{n<=k} c_n T_n(A) in (k products); s1, s2: scratch.
+hipError_t launch_chebyshev(SysDev& s, int k, const double* in_re, const double* in_im,
+                            double* out_re, double* out_im, double* s1_re, double* s1_im,
+                            double* s2_re, double* s2_im, hipStream_t st);
 // Crank-Nicolson step out = (I - A/2)^-1 (I + A/2) in with A the current
 // operator (destroyed); t: W N M scratch planes.
 hipError_t launch_crank_nicolson(SysDev& s, const double* in_re, const double* in_im,

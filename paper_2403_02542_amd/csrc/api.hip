@@ -390,6 +390,9 @@ afq_status exponential(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, const 
   else if (P.exp_method == AFQ_EXP_BLOCK_KRYLOV)
     HIPCHK(launch_block_krylov(s, P.exp_order, in_re, in_im, out_re, out_im, s.t3_re, s.t3_im,
                                  st));
+  else if (P.exp_method == AFQ_EXP_CHEBYSHEV)
+    HIPCHK(launch_chebyshev(s, P.exp_order, in_re, in_im, out_re, out_im, s.t3_re, s.t3_im,
+                            spare_re, spare_im, st));
   else
     HIPCHK(launch_taylor(s, P.exp_order, in_re, in_im, out_re, out_im, s.t3_re, s.t3_im,
                            spare_re, spare_im, st));
@@ -1248,7 +1251,7 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   if (!sys_ids || !P || n_sys < 1) return fail(ctx, AFQ_EINVAL, "bad arguments");
   if (!(P->tau > 0.0) || !std::isfinite(P->tau)) return fail(ctx, AFQ_EINVAL, "tau must be > 0");
   if (P->exp_method != AFQ_EXP_KRYLOV && P->exp_method != AFQ_EXP_TAYLOR &&
-      P->exp_method != AFQ_EXP_BLOCK_KRYLOV)
+      P->exp_method != AFQ_EXP_BLOCK_KRYLOV && P->exp_method != AFQ_EXP_CHEBYSHEV)
     return fail(ctx, AFQ_EINVAL, "unknown exp_method");
   if (P->exp_order < 1 || P->exp_order > 16) return fail(ctx, AFQ_EINVAL, "exp_order must be in [1, 16]");
   if (P->precision < AFQ_PREC_FP64 || P->precision > AFQ_PREC_MIXED_ENERGY)
@@ -1289,7 +1292,8 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
     if (P->exp_method == AFQ_EXP_BLOCK_KRYLOV && P->exp_order * ss[i]->N > ss[i]->M)
       return fail(ctx, AFQ_EINVAL, "block Krylov needs exp_order * N <= M");
     TRY(ensure_half_step(ctx, *ss[i], P->tau));
-    if (P->exp_method != AFQ_EXP_TAYLOR) TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
+    if (P->exp_method == AFQ_EXP_KRYLOV || P->exp_method == AFQ_EXP_BLOCK_KRYLOV)
+      TRY(ensure_krylov(ctx, sys_ids[i], *ss[i], P->exp_order));
     if (P->exp_method == AFQ_EXP_BLOCK_KRYLOV) TRY(ensure_bkrylov(ctx, *ss[i], P->exp_order));
     if (energy_pieces(P->precision))
       TRY(ensure_mixed(ctx, sys_ids[i], *ss[i], energy_pieces(P->precision)));

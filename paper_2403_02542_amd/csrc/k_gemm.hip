@@ -212,6 +212,9 @@ __global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int M,
 //   row (re, j): [ v_re[j][q],  -v_im[j][q] ],   row (im, j): [ v_im, v_re ]
 //   col p:       [ A_re[p][q],   A_im[p][q] ]
 // mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
+// mode 2 (Chebyshev T_1): out = A v and sum += c out (c = inv_n).
+// mode 3 (Chebyshev T_n): out = 2 A v - out (out holds T_{n-2} on entry, v
+// is T_{n-1}) and sum += c out.
 
 // Eight waves: two rows of waves split the 2N rows (RT = ceil(TR / 2) row
 // tiles each) and four columns of waves hold up to two column tiles each;
@@ -266,11 +269,12 @@ __global__ __launch_bounds__((MvCfg<RT>::NT)) void k_matvec(int W, int N, int M,
           const bool im_row = r >= N;
           const int j = im_row ? r - N : r;
           const int64_t off = (int64_t)w * o.sw + (int64_t)j * o.sj + c0 + c;
-          if (mode == 1) {
-            val *= inv_n;
+          if (mode == 3) val = 2.0 * val - (im_row ? o.im[off] : o.re[off]);
+          if (mode >= 1) {
+            const double add = mode == 1 ? (val *= inv_n) : inv_n * val;
             const int64_t soff = (int64_t)w * sum.sw + (int64_t)j * sum.sj + c0 + c;
-            if (im_row) sum.im[soff] += val;
-            else sum.re[soff] += val;
+            if (im_row) sum.im[soff] += add;
+            else sum.re[soff] += add;
           }
           if (im_row) o.im[off] = val;
           else o.re[off] = val;
@@ -668,6 +672,66 @@ void op_blocks(int M, int R, std::vector<int2>& out) {
 hipError_t launch_opbuild(SysDev& s, hipStream_t st) {
   if (s.op_pieces == 0) return opbuild_fp64(s, st);
   return launch_opbuild_mx(s, st);   // operator pieces for the BF16-split products
+}
+
+// out = a in, y = in (the first term of the Chebyshev sum and T_0).
+__global__ void k_cheb_init(int64_t n, double a, const double* __restrict__ ire,
+                            const double* __restrict__ iim, double* __restrict__ ore,
+                            double* __restrict__ oim, double* __restrict__ yre,
+                            double* __restrict__ yim) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double r = ire[e], i = iim[e];
+    ore[e] = a * r;
+    oim[e] = a * i;
+    yre[e] = r;
+    yim[e] = i;
+  }
+}
+
+// Coefficients of the Chebyshev expansion of the exponential (Sec. IV.B):
+// c_0 = J_0(i), c_n = 2 i^n J_n(-i).  With J_n(i z) = i^n I_n(z) both are
+// real: c_0 = I_0(1), c_n = 2 I_n(1), from the power series
+// I_n(1) = sum_m (1/2)^(2m + n) / (m! (m + n)!).
+double cheb_coef(int n) {
+  double term = 1.0;
+  for (int q = 1; q <= n; ++q) term *= 0.5 / q;   // (1/2)^n / n!
+  double sum = 0.0;
+  for (int m = 0; m < 40; ++m) {
+    sum += term;
+    term *= 0.25 / ((m + 1.0) * (m + 1.0 + n));
+  }
+  return n == 0 ? sum : 2.0 * sum;
+}
+
+hipError_t launch_chebyshev(SysDev& s, int k, const double* in_re, const double* in_im,
+                            double* out_re, double* out_im, double* s1_re, double* s1_im,
+                            double* s2_re, double* s2_im, hipStream_t st) {
+  const int64_t sw = (int64_t)s.N * s.M, sj = s.M, n = sw * s.W;
+  const int64_t g = (n + 255) / 256;
+  // out = c_0 T_0, s2 = T_0
+  hipLaunchKernelGGL(k_cheb_init, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, st, n,
+                     cheb_coef(0), in_re, in_im, out_re, out_im, s2_re, s2_im);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || k < 1) return e;
+  // s1 = T_1 = A T_0, out += c_1 T_1
+  VecOut sum{out_re, out_im, sw, sj};
+  e = run_matvec(s, VecRef{in_re, in_im, sw, sj}, VecOut{s1_re, s1_im, sw, sj}, 2, cheb_coef(1),
+                 sum, st);
+  if (e != hipSuccess) return e;
+  // T_n = 2 A T_{n-1} - T_{n-2} over the older buffer, out += c_n T_n
+  double* cur_re = s1_re;
+  double* cur_im = s1_im;
+  double* old_re = s2_re;
+  double* old_im = s2_im;
+  for (int m = 2; m <= k; ++m) {
+    e = run_matvec(s, VecRef{cur_re, cur_im, sw, sj}, VecOut{old_re, old_im, sw, sj}, 3,
+                   cheb_coef(m), sum, st);
+    if (e != hipSuccess) return e;
+    std::swap(cur_re, old_re);
+    std::swap(cur_im, old_im);
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_taylor(SysDev& s, int k, const double* in_re, const double* in_im,

@@ -717,11 +717,13 @@ __global__ __launch_bounds__(MT_) void k_matvec_mx(int W, int N, int M, int Kq, 
         double val = (double)acc[i][j][e];
         const int64_t pcol = row0 + r;
         const int64_t off = (int64_t)w * o.sw + (int64_t)jo * o.sj + pcol;
-        if (mode == 1) {
-          val *= inv_n;
+        // modes as in the FP64 product (k_matvec)
+        if (mode == 3) val = 2.0 * val - (im_row ? o.im[off] : o.re[off]);
+        if (mode >= 1) {
+          const double add = mode == 1 ? (val *= inv_n) : inv_n * val;
           const int64_t soff = (int64_t)w * sum.sw + (int64_t)jo * sum.sj + pcol;
-          if (im_row) sum.im[soff] += val;
-          else sum.re[soff] += val;
+          if (im_row) sum.im[soff] += add;
+          else sum.re[soff] += add;
         }
         if (im_row) o.im[off] = val;
         else o.re[off] = val;
