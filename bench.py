@@ -66,9 +66,9 @@ def measured_traffic(cfg, precision):
     if precision != "fp64" or cfg.name != "c3" or cfg.W != 512 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
-        return None
+    for src, sha in rec["sources"].items():
+        if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != sha:
+            return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 

@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libafq.so")
 
 SOURCES = ["api.hip", "k_gemm.hip", "k_walker.hip", "k_exchange.hip", "k_mixed.hip", "k_adjoint.hip",
-           "k_bkrylov.hip", "k_cn.hip", "jacobi.cpp", "stats.cpp"]
+           "k_bkrylov.hip", "k_cn.hip", "k_coulomb.hip", "jacobi.cpp", "stats.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

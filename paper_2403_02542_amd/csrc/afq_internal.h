@@ -39,6 +39,7 @@ struct SysDev {
   double* psiv = nullptr;
   double* Lov = nullptr;
   double* T0 = nullptr;
+  double* t0tr = nullptr;     // [G] 2 tr T0_g (the trial part of ell_g)
   double* lbar = nullptr;     // [G]
   double* H1 = nullptr;       // [M][M]
   double* Bhalf = nullptr;    // [M][M] exp(-tau H1 / 2)
@@ -353,6 +354,14 @@ hipError_t launch_matvec_probe(SysDev& s, const double* in_re, const double* in_
 // steps that do not measure the energy and after a BF16-split local energy.
 // part: scratch of coulomb_slices(W, G, N M) x W x G doubles.
 int coulomb_slices(int W, int G, int NM);
+// The same Coulomb vector from the projected Theta_v (virtual space, K = N Kv):
+// ell_g = 2 tr T0_g + 2 sum_(i,k) Lov_g[i][k] Theta_v[i][k]; part: scratch of
+// coulomb_v_slices(W, G, N, Kv) x W x G doubles.
+int coulomb_v_slices(int W, int G, int N, int Kv);
+hipError_t launch_coulomb_v(SysDev& s, const double* thv_re, const double* thv_im, double* part,
+                            double* ell_re, double* ell_im, hipStream_t st);
+// t0tr[g] = 2 tr T0_g for g < G.
+hipError_t launch_t0_trace(SysDev& s, hipStream_t st);
 hipError_t launch_coulomb(SysDev& s, const double* th_re, const double* th_im, double* part,
                           double* ell_re, double* ell_im, hipStream_t st);
 // Admissible (GA, WB) tile shapes for N, best first by the occupancy model.

@@ -238,7 +238,8 @@ afq_status ensure_krylov(afq_ctx* ctx, int32_t sid, SysDev& s, int k) {
 afq_status ensure_coulomb(afq_ctx* ctx, SysDev& s) {
   if (s.coul_ws) return AFQ_OK;
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  const size_t n = (size_t)coulomb_slices(s.W, s.G, s.N * s.M) * s.W * s.G;
+  const int S1 = coulomb_slices(s.W, s.G, s.N * s.M), S2 = coulomb_v_slices(s.W, s.G, s.N, s.Kv);
+  const size_t n = (size_t)(S1 > S2 ? S1 : S2) * s.W * s.G;
   TRY(dalloc(ctx, s.walker_allocs, &s.coul_ws, n));
   ++s.gen;
   return AFQ_OK;
@@ -507,8 +508,9 @@ afq_status step_exchange(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, hipS
                               s.thb, st));
     HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.ell_re, s.ell_im, s.ex_re, s.ex_im, st));
     // the force bias of the next step (and the Hartree term) from the FP64
-    // Coulomb vector: the walkers follow the FP64 trajectory
-    HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, s.ell_re, s.ell_im, st));
+    // Coulomb vector over the virtual space: the walkers follow the FP64
+    // trajectory
+    HIPCHK(launch_coulomb_v(s, s.thv_re, s.thv_im, s.coul_ws, s.ell_re, s.ell_im, st));
   }
   return AFQ_OK;
 }
@@ -1076,6 +1078,7 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
     TRY(dalloc(ctx, own, &s.psiv, pv.size()));
     TRY(dalloc(ctx, own, &s.Lov, (size_t)(G + 1) * N * s.Kv));
     TRY(dalloc(ctx, own, &s.T0, (size_t)(G + 1) * N * N));
+    TRY(dalloc(ctx, own, &s.t0tr, (size_t)G));
     if (!pv.empty())
       HIPCHK(hipMemcpy(s.psiv, pv.data(), pv.size() * 8, hipMemcpyHostToDevice));
     GemmArgs q{};
@@ -1086,6 +1089,7 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
     HIPCHK(launch_gemm(q, ctx->stream));
     q.B = s.psit; q.C = s.T0; q.sCr = N; q.Cn = N;
     HIPCHK(launch_gemm(q, ctx->stream));
+    HIPCHK(launch_t0_trace(s, ctx->stream));
   }
   // H1 = h - 1/2 sum_g L_g L_g + sum_g Lbar_g L_g
   HIPCHK(hipMemcpyAsync(s.H1, s.h, MM * 8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1458,7 +1462,7 @@ afq_status afq_local_energy_batch(afq_ctx* ctx, int32_t sys_id, int32_t precisio
     HIPCHK(launch_exchange_mx(s, s.W, s.thb, s.thb_ps, s.mell_re, s.mell_im, s.mex_re, s.mex_im,
                               ctx->stream));
     TRY(ensure_coulomb(ctx, s));
-    HIPCHK(launch_coulomb(s, s.th_re, s.th_im, s.coul_ws, s.mell_re, s.mell_im, ctx->stream));
+    HIPCHK(launch_coulomb_v(s, s.thv_re, s.thv_im, s.coul_ws, s.mell_re, s.mell_im, ctx->stream));
     HIPCHK(launch_energy(s, s.W, s.mell_re, s.mell_im, s.mex_re, s.mex_im, s.eloc, nullptr,
                          nullptr, 0.0, ctx->stream));
   }
