@@ -505,6 +505,9 @@ def main():
     sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
     ctx.init_trial(sid, psi)
     ctx.init_walkers(sid, cfg.W)
+    if args.autotune:
+        log("autotuning tiles")
+        ctx.autotune([sid])
     step0 = 0
 
     def run_mode(name, energy_every=None, tau=None):
@@ -612,6 +615,7 @@ def main():
                    "M": cfg.M, "N": cfg.N, "n_chol": cfg.G, "walkers": cfg.W, "k": cfg.k,
                    "tau": cfg.tau, "reorth_every": cfg.reorth_every,
                    "precision": args.precision, "energy_every": args.energy_every,
+                   "autotune": bool(args.autotune),
                    "parallelism": "1 GPU"},
         "step_tflops": step_fl / (ms_per_step / 1e3) / 1e12,
         "step_frac_fp64_peak": step_fl / (ms_per_step / 1e3) / PEAK_FP64,

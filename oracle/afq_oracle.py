@@ -205,25 +205,25 @@ def arnoldi(A: np.ndarray, psi: np.ndarray, k: int):
     breakdown (the residual vanishes against ||A b_j||)."""
     M = psi.shape[0]
     beta = np.linalg.norm(psi)
-    Bk = np.zeros((M, k), dtype=complex)
+    V = np.zeros((k, M), dtype=complex)      # basis vectors as rows (contiguous)
     Hk = np.zeros((k, k), dtype=complex)
     if beta == 0.0:
-        return Bk[:, :0], Hk[:0, :0], 0.0
-    Bk[:, 0] = psi / beta
+        return V[:0].T, Hk[:0, :0], 0.0
+    V[0] = psi / beta
     for j in range(k):
-        w = A @ Bk[:, j]
+        w = A @ V[j]
         wnorm = np.linalg.norm(w)
         for i in range(j + 1):
-            Hk[i, j] = np.vdot(Bk[:, i], w)
-            w = w - Hk[i, j] * Bk[:, i]
+            Hk[i, j] = np.vdot(V[i], w)
+            w = w - Hk[i, j] * V[i]
         if j + 1 == k:
             break
         hn = np.linalg.norm(w)
         if hn <= KRYLOV_BREAKDOWN_REL * wnorm or hn == 0.0:
-            return Bk[:, :j + 1], Hk[:j + 1, :j + 1], beta
+            return V[:j + 1].T, Hk[:j + 1, :j + 1], beta
         Hk[j + 1, j] = hn
-        Bk[:, j + 1] = w / hn
-    return Bk, Hk, beta
+        V[j + 1] = w / hn
+    return V.T, Hk, beta
 
 
 def krylov_vector(A: np.ndarray, psi: np.ndarray, k: int) -> np.ndarray:

@@ -84,14 +84,17 @@ __global__ void k_zero2(int64_t n, double* __restrict__ a, double* __restrict__ 
   }
 }
 
-// max over walkers (alive, finite) of ||A_k||_1 = max_c sum_r |A_k[r][c]|,
-// as the bit pattern of a non-negative double.
+// max over walkers (alive, factorised, finite) of ||A_k||_1 =
+// max_c sum_r |A_k[r][c]|, as the bit pattern of a non-negative double.  A
+// walker whose block factorisation failed is poisoned afterwards; its A_k
+// must not set the substep count of the others.
 __global__ __launch_bounds__(256) void k_norm1(int D, const double* __restrict__ hre,
                                                const double* __restrict__ him,
                                                const int* __restrict__ alive,
+                                               const int* __restrict__ bad,
                                                unsigned long long* __restrict__ out) {
   const int b = blockIdx.x;
-  if (!alive[b]) return;
+  if (!alive[b] || bad[b]) return;
   const double* r0 = hre + (int64_t)b * D * D;
   const double* i0 = him + (int64_t)b * D * D;
   double m = 0.0;
@@ -204,7 +207,8 @@ hipError_t launch_block_krylov(SysDev& s, int k, const double* in_re, const doub
   }
   // substeps of the small exponential from the largest ||A_k||_1
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, s.bk_norm);
-  hipLaunchKernelGGL(k_norm1, dim3(W), dim3(256), 0, st, D, s.bkh_re, s.bkh_im, s.alive, s.bk_norm);
+  hipLaunchKernelGGL(k_norm1, dim3(W), dim3(256), 0, st, D, s.bkh_re, s.bkh_im, s.alive, s.bk_bad,
+                     s.bk_norm);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   unsigned long long nb = 0;
   if ((e = hipMemcpyAsync(&nb, s.bk_norm, sizeof(nb), hipMemcpyDeviceToHost, st)) != hipSuccess)

@@ -9,8 +9,12 @@ if ROOT not in sys.path:
 
 
 def pytest_sessionstart(session):
-    # The oracle's many small BLAS calls run fastest on one thread.
+    # The oracle's many small BLAS calls run fastest on one thread (with one
+    # thread per core they are ~20x slower).  threadpoolctl limits only the
+    # libraries already loaded, so numpy and scipy are imported first.
     try:
+        import numpy  # noqa: F401
+        import scipy.linalg  # noqa: F401
         from threadpoolctl import threadpool_limits
         session._afq_blas_limit = threadpool_limits(1)
     except Exception:
