@@ -145,7 +145,16 @@ typedef struct {
                             weight 1; T = 0 leaves the walkers alone             */
   int32_t propagator;    /* AFQ_PROP_*: the orbital update of a step (Sec. III);
                             all but SPLIT2 need precision FP64 or MIXED_ENERGY  */
+  int32_t force_bias_at; /* AFQ_FB_START: f from the Green's function of the
+                            walker at the start of the step (default).
+                            AFQ_FB_HALF: f from that of exp(-tau H1/2) Phi,
+                            after the first Split-2 half-step (SPLIT2 only;
+                            one more overlap and Coulomb-vector product per
+                            step).  The paper does not place f (Eq.
+                            force_shift); any f is a change of variables of
+                            the field integral                                  */
 } afq_prop_params;
+enum { AFQ_FB_START = 0, AFQ_FB_HALF = 1 };
 
 /* Propagators (Sec. III), with A = -tau H_int^w and H1 the effective
  * one-body matrix (h - 1/2 sum_g L_g L_g + sum_g Lbar_g L_g):

@@ -476,20 +476,33 @@ def propagate_orbitals(p: Prepared, phi: np.ndarray, A: np.ndarray, method: int,
     raise ValueError(f"unknown propagator {prop}")
 
 
+FB_START, FB_HALF = 0, 1
+
+
 def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
-                reorth: bool, prop: int = PROP_SPLIT2):
+                reorth: bool, prop: int = PROP_SPLIT2, fb_at: int = FB_START):
     """One step of one walker (Split-2 unless `prop` says otherwise):
     returns (new walker, StepInfo).
 
     Order: force bias at the start-of-step Green's function (Reading: the
-    paper does not say where f is evaluated), operator, the orbital update
-    of `propagate_orbitals`, overlap and weight, optional
-    reorthonormalisation, local energy of the new determinant."""
+    paper does not say where f is evaluated; fb_at = FB_HALF evaluates it at
+    Phi' = exp(-tau H1/2) Phi after the first Split-2 half-step instead, the
+    alternative placement), operator, the orbital update of
+    `propagate_orbitals`, overlap and weight, optional reorthonormalisation,
+    local energy of the new determinant.  Any f is a change of variables of
+    the field integral, so both placements sample the same propagator."""
     if not wk.alive:
         e = local_energy(p, wk.phi, wk.theta)
         return wk, StepInfo(e, capped_energy(e, p.e0, 2 * p.N, p.tau),
                             0j, 0.0, 0j, 0, np.zeros(p.G, complex))
-    ell = coulomb_vector(p, wk.theta)
+    if fb_at == FB_HALF:
+        if prop != PROP_SPLIT2:
+            raise ValueError("the half-step force bias belongs to the Split-2 propagator")
+        _, theta_half = overlap(p.psi_t, p.B @ wk.phi)
+        ell = (coulomb_vector(p, theta_half) if theta_half is not None
+               else np.full(p.G, complex(np.nan)))
+    else:
+        ell = coulomb_vector(p, wk.theta)
     f, fbar = force_bias(p, ell)
     A, s_mf, log_i = interaction_operator(p, x, fbar)
     phi = propagate_orbitals(p, wk.phi, A, method, k, prop)
@@ -525,7 +538,7 @@ def reorth_due(step: int, every: int) -> bool:
 
 def run(p: Prepared, walkers, fields_of_step, n_steps: int, method: int,
         k: int, reorth_every: int, step0: int = 0, e0_state: E0State = None,
-        pop_every: int = 0, comb_u=None, prop: int = PROP_SPLIT2):
+        pop_every: int = 0, comb_u=None, prop: int = PROP_SPLIT2, fb_at: int = FB_START):
     """Propagate a list of walkers; fields_of_step(t) -> (W, G) array.
 
     Returns (walkers, history) where history[s] holds per-walker arrays of
@@ -542,7 +555,8 @@ def run(p: Prepared, walkers, fields_of_step, n_steps: int, method: int,
         infos = []
         new = []
         for w, wk in enumerate(walkers):
-            nw, info = walker_step(p, wk, x[w], method, k, reorth_due(t, reorth_every), prop)
+            nw, info = walker_step(p, wk, x[w], method, k, reorth_due(t, reorth_every), prop,
+                                   fb_at)
             new.append(nw)
             infos.append(info)
         walkers = new

@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libafq.so"
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = range(6)
 EXP_KRYLOV, EXP_TAYLOR, EXP_BLOCK_KRYLOV, EXP_CHEBYSHEV = 0, 1, 2, 3
 PROP_SPLIT2, PROP_SPLIT1, PROP_TAYLOR, PROP_CN = 0, 1, 2, 3
+FB_START, FB_HALF = 0, 1
 PREC_FP64, PREC_MIXED, PREC_MIXED_FAST, PREC_MIXED_ENERGY = 0, 1, 2, 3
 SCHED_AUTO, SCHED_SERIAL, SCHED_STREAMS, SCHED_GRAPH = 0, 1, 2, 3
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENUMERIC"}
@@ -61,6 +62,7 @@ class PropParams(ctypes.Structure):
         ("e0_window", ctypes.c_int32),
         ("pop_every", ctypes.c_int32),
         ("propagator", ctypes.c_int32),
+        ("force_bias_at", ctypes.c_int32),
     ]
 
 
@@ -243,7 +245,7 @@ class Context:
     def propagate_batch(self, sys_ids, *, tau, n_steps, exp_method=EXP_KRYLOV, exp_order=6,
                         reorth_every=1, precision=PREC_FP64, energy_every=1, e0=None, seed=0,
                         step0=0, fields=None, energies_out=None, schedule=SCHED_AUTO,
-                        e0_window=0, pop_every=0, propagator=0):
+                        e0_window=0, pop_every=0, propagator=0, force_bias_at=0):
         ids = [sys_ids] if isinstance(sys_ids, int) else list(sys_ids)
         arr = (ctypes.c_int32 * len(ids))(*ids)
         fp, fdev, fk = _arg(fields, np.float64)
@@ -255,7 +257,8 @@ class Context:
         prm = PropParams(float(tau), int(exp_method), int(exp_order), int(reorth_every),
                          int(precision), int(n_steps), int(energy_every),
                          math.nan if e0 is None else float(e0), int(seed), int(step0), fp, ep,
-                         int(schedule), int(e0_window), int(pop_every), int(propagator))
+                         int(schedule), int(e0_window), int(pop_every), int(propagator),
+                         int(force_bias_at))
         self._check(self._lib.afq_propagate_batch(self._h, arr, len(ids), ctypes.byref(prm)))
 
     def autotune(self, sys_ids, reps: int = 3, **_ignored):

@@ -403,6 +403,22 @@ afq_status exponential(afq_ctx* ctx, SysDev& s, const afq_prop_params& P, const 
 afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_params& P,
                       const double* x_given, uint64_t t, const CallState* cs, int add,
                       hipStream_t st) {
+  const bool half_fb = P.force_bias_at == AFQ_FB_HALF;
+  if (half_fb) {
+    // the force bias from Phi' = exp(-tau H1/2) Phi: Theta' and the Coulomb
+    // vector at Phi' (the proposed-state buffers serve as scratch; the back
+    // half of the step overwrites them)
+    {
+      Phase ph(ctx, AFQ_PH_ONEBODY);
+      HIPCHK(launch_onebody(s, s.phi_re, s.phi_im, s.t1_re, s.t1_im, st));
+    }
+    {
+      Phase ph(ctx, AFQ_PH_OVERLAP);
+      HIPCHK(launch_overlap(s, s.W, s.t1_re, s.t1_im, s.logdet_n, s.thn_re, s.thn_im, s.bad, st));
+    }
+    Phase ph(ctx, AFQ_PH_COULOMB);
+    HIPCHK(launch_coulomb(s, s.thn_re, s.thn_im, s.coul_ws, s.ell_re, s.ell_im, st));
+  }
   const double* x = s.x;
   if (x_given) {
     x = x_given;
@@ -435,8 +451,10 @@ afq_status step_front(afq_ctx* ctx, int32_t sid, SysDev& s, const afq_prop_param
   const double* in_re = s.phi_re;
   const double* in_im = s.phi_im;
   if (P.propagator == AFQ_PROP_SPLIT2) {
-    Phase ph(ctx, AFQ_PH_ONEBODY);
-    HIPCHK(launch_onebody(s, s.phi_re, s.phi_im, s.t1_re, s.t1_im, st));
+    if (!half_fb) {
+      Phase ph(ctx, AFQ_PH_ONEBODY);
+      HIPCHK(launch_onebody(s, s.phi_re, s.phi_im, s.t1_re, s.t1_im, st));
+    }
     in_re = s.t1_re;
     in_im = s.t1_im;
   }
@@ -839,6 +857,7 @@ afq_status run_graph(afq_ctx* ctx, const int32_t* ids, const std::vector<SysDev*
   put_bytes(key, P.e0_window);
   put_bytes(key, P.pop_every);
   put_bytes(key, P.propagator);
+  put_bytes(key, P.force_bias_at);
   afq_ctx::GraphEntry* ge = nullptr;
   for (auto& g : ctx->graphs)
     if (g.key == key) ge = &g;
@@ -1267,6 +1286,10 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
   if (P->pop_every < 0) return fail(ctx, AFQ_EINVAL, "pop_every < 0");
   if (P->propagator < AFQ_PROP_SPLIT2 || P->propagator > AFQ_PROP_CN)
     return fail(ctx, AFQ_EINVAL, "unknown propagator");
+  if (P->force_bias_at != AFQ_FB_START && P->force_bias_at != AFQ_FB_HALF)
+    return fail(ctx, AFQ_EINVAL, "unknown force_bias_at");
+  if (P->force_bias_at == AFQ_FB_HALF && P->propagator != AFQ_PROP_SPLIT2)
+    return fail(ctx, AFQ_EINVAL, "the half-step force bias belongs to the Split-2 propagator");
   if (P->propagator != AFQ_PROP_SPLIT2 && op_pieces_of(P->precision) > 0)
     return fail(ctx, AFQ_EINVAL, "Split-1, the refactorised and the Crank-Nicolson propagators "
                                  "run with FP64 propagation (precision FP64 or MIXED_ENERGY)");
@@ -1323,7 +1346,8 @@ afq_status afq_propagate_batch(afq_ctx* ctx, const int32_t* sys_ids, int32_t n_s
         HIPCHK(launch_split_lt(s, ctx->stream));
       }
     }
-    if (P->energy_every > 1 || energy_pieces(P->precision)) TRY(ensure_coulomb(ctx, *ss[i]));
+    if (P->energy_every > 1 || energy_pieces(P->precision) || P->force_bias_at == AFQ_FB_HALF)
+      TRY(ensure_coulomb(ctx, *ss[i]));
     HIPCHK(launch_zero_counters(*ss[i], ctx->stream));
     if (!std::isnan(P->e0)) HIPCHK(launch_set_e0(*ss[i], P->e0, ctx->stream));
   }

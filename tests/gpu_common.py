@@ -95,7 +95,7 @@ def flags_from_info(p, info, weight_factor_ok=True):
 
 
 def run_pair(case, ctx, *, tau, k, method, reorth, n_steps, n_walkers, track, seed=0,
-             phi0=None, resync=False, live_only=False, stats=None, prop=0):
+             phi0=None, resync=False, live_only=False, stats=None, prop=0, fb_at=0):
     """Propagate n_walkers on the GPU and the `track` subset in the oracle,
     one step per call, on the same fields; returns the worst errors.
 
@@ -123,13 +123,14 @@ def run_pair(case, ctx, *, tau, k, method, reorth, n_steps, n_walkers, track, se
         x = W.fields(seed, 0, s, n_walkers, case.G)
         xd = to_dev(x)
         ctx.propagate_batch(sid, tau=tau, n_steps=1, exp_method=method, exp_order=k,
-                            reorth_every=reorth, step0=s, fields=xd, e0=p.e0, propagator=prop)
+                            reorth_every=reorth, step0=s, fields=xd, e0=p.e0, propagator=prop,
+                            force_bias_at=fb_at)
         torch.cuda.synchronize()
         st = ctx.get_walkers(sid)
         el = ctx.local_energy_batch(sid)
         for t, w in enumerate(track):
             wks[t], info = O.walker_step(p, wks[t], x[w], method, k, O.reorth_due(s, reorth),
-                                         prop)
+                                         prop, fb_at)
             if flags_from_info(p, info):
                 flagged.add(w)
             if w in flagged or w in dead:

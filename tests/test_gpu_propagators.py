@@ -129,3 +129,51 @@ def test_size_consistency_direct_sum(ctx, prop):
     print(f"propagator {prop}: phi {worst_phi:.2e}, log overlap {worst_ld:.2e}, E_L {worst_el:.2e}; "
           f"E_s per step (Ha) {np.round(ek['AB'] - ek['A'] - ek['B'], 5)}", flush=True)
     assert worst_phi < C.RTOL and worst_ld < C.RTOL and worst_el < C.RTOL
+
+
+@pytest.mark.parametrize("cfg_name,track,steps", [("c1", list(range(16)), 20),
+                                                  ("c2", [3, 250], 10)])
+def test_half_step_force_bias(ctx, cfg_name, track, steps):
+    """Force bias from the Green's function of exp(-tau H1/2) Phi (the
+    alternative placement) against the oracle's step with fb_at = FB_HALF."""
+    cfg = W.CONFIGS[cfg_name]
+    case = C.Case.from_config(cfg_name)
+    worst, flagged, _ = C.run_pair(case, ctx, tau=cfg.tau, k=cfg.k, method=O.EXP_KRYLOV,
+                                   reorth=cfg.reorth_every, n_steps=steps, n_walkers=cfg.W,
+                                   track=track, fb_at=O.FB_HALF)
+    print(cfg_name, "half-step force bias", worst, "flagged", sorted(flagged))
+    assert len(flagged) <= 2
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
+def test_half_step_force_bias_schedules_agree(ctx):
+    """Three systems under the graph schedule with the half-step force bias
+    equal each system propagated alone, bitwise."""
+    import torch
+    from paper_2403_02542_amd import afq
+    batch = W.make_uneven_batch(W.UnevenBatch("fb3", n_sys=3, W=6, tau=0.05, k=5, steps=4,
+                                              reorth_every=2, m_lo=20, m_hi=60, seed=7))
+    res = []
+    for sched, alone in ((afq.SCHED_SERIAL, True), (afq.SCHED_GRAPH, False)):
+        c = afq.Context(0)
+        ids = []
+        for cfg_, ham, psi in batch:
+            s = c.init_hamiltonian(ham.h, ham.L, ham.e_core)
+            c.init_trial(s, psi)
+            c.init_walkers(s, 6)
+            ids.append(s)
+        kw = dict(tau=0.05, n_steps=4, exp_order=5, reorth_every=2, seed=1, schedule=sched,
+                  force_bias_at=afq.FB_HALF)
+        if alone:
+            for s in ids:
+                c.propagate_batch(s, **kw)
+        else:
+            c.propagate_batch(ids, **kw)
+        c.sync()
+        torch.cuda.synchronize()
+        res.append([c.get_walkers(s) for s in ids])
+        c.close()
+    for a, b in zip(res[0], res[1]):
+        for key in ("phi", "weight", "log_ovlp"):
+            assert np.array_equal(a[key], b[key]), key

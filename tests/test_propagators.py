@@ -168,3 +168,59 @@ def test_crank_nicolson_error_scaling():
         diffs.append(np.abs(a - b).max())
     print(diffs, diffs[0] / diffs[1], diffs[1] / diffs[2])
     assert diffs[1] / diffs[2] == pytest.approx(8.0, rel=0.15)
+
+
+@pytest.mark.parametrize("fb_at", [O.FB_START, O.FB_HALF])
+def test_force_bias_placement_is_a_change_of_variables(fb_at):
+    """One Cholesky vector (the HS transform is exact): whether f is taken at
+    the start of the step or at the half-step orbitals, the Gauss-Hermite
+    average over x of exp(-tau (E_H(x) - E0)) |Phi'(x)> / <Psi_T|Phi'(x)>
+    from the oracle's own step equals the split propagator in Fock space;
+    the two placements differ in f (so in the samples), not in the average."""
+    import fock
+    M, N, G = 4, 2, 1
+    rng = np.random.default_rng(31)
+    A0 = rng.normal(size=(M, M)) * 0.5
+    h = np.diag(rng.uniform(-2, 0, M)) + 0.05 * (A0 + A0.T)
+    L = (lambda a: (a + a.T)[None])(rng.normal(size=(M, M)) * 0.5)
+    psi, _ = np.linalg.qr(rng.normal(size=(M, N)))
+    tau = 0.3
+    p = O.prepare(h, L, 0.1, psi, tau)
+    phi = psi + 0.3 * (rng.normal(size=(M, N)) + 1j * rng.normal(size=(M, N)))
+    wk = O.init_walker(p, phi)
+    xs, ws = np.polynomial.hermite_e.hermegauss(90)
+    ws = ws / math.sqrt(2 * math.pi)
+    t = fock.determinant(psi.astype(complex))
+    acc = np.zeros(1 << (2 * M), dtype=complex)
+    fs = set()
+    for x, wq in zip(xs, ws):
+        new, info = O.walker_step(p, wk, np.array([x]), O.EXP_KRYLOV, M, False,
+                                  O.PROP_SPLIT2, fb_at)
+        fs.add(complex(info.f[0]))
+        v = fock.determinant(new.phi)
+        acc += wq * np.exp(-tau * (info.e_hybrid - p.e0)) * v / np.vdot(t, v)
+    assert len(fs) == 1 and abs(fs.pop()) > 0.05
+    dim = 1 << (2 * M)
+    Bh = scipy.linalg.expm(-0.5 * tau * fock.one_body(p.H1, M).toarray())
+    X = fock.one_body(L[0], M).toarray() - p.lbar[0] * np.eye(dim)
+    U = math.exp(-tau * (p.e_const - p.e0)) * Bh @ scipy.linalg.expm(-0.5 * tau * X @ X) @ Bh
+    v0 = fock.determinant(wk.phi)
+    ref = U @ v0 / np.vdot(t, v0)
+    assert np.abs(acc - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_force_bias_placements_differ():
+    """The half-step force bias is not the start-of-step one (a walker away
+    from the trial): the placement is a real option, not a no-op."""
+    M, N, G = 10, 3, 12
+    h, L, psi = _system(M, N, G, seed=8, scale=1.0)
+    p = O.prepare(h, L, 0.0, psi, tau=0.1)
+    rng = np.random.default_rng(2)
+    phi = psi + 0.3 * (rng.normal(size=(M, N)) + 1j * rng.normal(size=(M, N)))
+    wk = O.init_walker(p, phi)
+    x = rng.normal(size=G)
+    _, a = O.walker_step(p, wk, x, O.EXP_KRYLOV, 6, False, O.PROP_SPLIT2, O.FB_START)
+    _, b = O.walker_step(p, wk, x, O.EXP_KRYLOV, 6, False, O.PROP_SPLIT2, O.FB_HALF)
+    assert np.abs(a.f - b.f).max() > 1e-3
+    with pytest.raises(ValueError):
+        O.walker_step(p, wk, x, O.EXP_KRYLOV, 6, False, O.PROP_SPLIT1, O.FB_HALF)
