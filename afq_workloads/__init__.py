@@ -24,5 +24,6 @@ from .generate import (  # noqa: F401
     make_system,
     make_uneven_batch,
     rhf_trial,
+    spin_orbital_system,
     uneven_batch_sizes,
 )

@@ -120,6 +120,26 @@ def rhf_trial(h: np.ndarray, L: np.ndarray, N: int, n_iter: int = 10,
     return occupied(F)
 
 
+def spin_orbital_system(h: np.ndarray, L: np.ndarray, psi_a: np.ndarray,
+                        psi_b: np.ndarray):
+    """The same Hamiltonian in the basis of 2M spin orbitals (alpha block,
+    then beta): h and every L_g repeated on the diagonal, and the occupied
+    spin orbitals of an open-shell determinant, Psi = diag(Psi_a, Psi_b)
+    (M x N_a and M x N_b blocks; 2M x (N_a + N_b)).  Input layout only."""
+    M, G = h.shape[0], L.shape[0]
+    Na, Nb = psi_a.shape[1], psi_b.shape[1]
+    h2 = np.zeros((2 * M, 2 * M))
+    h2[:M, :M] = h
+    h2[M:, M:] = h
+    L2 = np.zeros((G, 2 * M, 2 * M))
+    L2[:, :M, :M] = L
+    L2[:, M:, M:] = L
+    psi = np.zeros((2 * M, Na + Nb))
+    psi[:M, :Na] = psi_a
+    psi[M:, Na:] = psi_b
+    return h2, L2, psi
+
+
 def fields(seed: int, sys_id: int, step: int, n_walkers: int,
            n_chol: int) -> np.ndarray:
     """Auxiliary fields x[w, g] ~ N(0, 1) of one step, shape (W, G)."""

@@ -44,15 +44,16 @@ KRYLOV_BREAKDOWN_REL = 1e-12
 # Setup: Sec. II.A (Eq. mbham, hstrafo, heffTOT, force_shift) and Sec. III.B
 # --------------------------------------------------------------------------
 
-def mean_field_shift(L: np.ndarray, psi_t: np.ndarray) -> np.ndarray:
+def mean_field_shift(L: np.ndarray, psi_t: np.ndarray, spin: int = 2) -> np.ndarray:
     """Lbar_g = <Psi_T|L_g|Psi_T> / <Psi_T|Psi_T>  (Eq. force_shift).
 
     For a restricted closed-shell determinant with orthonormal orbitals both
-    spins contribute tr(Psi_T^T L_g Psi_T)."""
+    spins contribute tr(Psi_T^T L_g Psi_T) (spin = 2); a determinant of spin
+    orbitals (spin = 1, open shell) counts each orbital once."""
     G = L.shape[0]
     out = np.empty(G)
     for g in range(G):
-        out[g] = 2.0 * np.trace(psi_t.T @ L[g] @ psi_t)
+        out[g] = spin * np.trace(psi_t.T @ L[g] @ psi_t)
     return out
 
 
@@ -96,6 +97,7 @@ class Prepared:
     h_half: np.ndarray        # Psi_T^T h          (N, M)
     L_half: np.ndarray        # Psi_T^T L_g        (G, N, M)
     e0: float                 # fixed trial energy (Reading: E0 = E_L(Psi_T))
+    spin: int = 2             # 2: closed shell, one spin block; 1: spin orbitals
 
     @property
     def M(self):
@@ -110,14 +112,21 @@ class Prepared:
         return self.L.shape[0]
 
 
-def prepare(h, L, e_core, psi_t, tau, e0=None) -> Prepared:
-    lbar = mean_field_shift(L, psi_t)
+def prepare(h, L, e_core, psi_t, tau, e0=None, spin=2) -> Prepared:
+    """spin = 2: restricted closed shell (h, L spatial, Psi_T the doubly
+    occupied orbitals).  spin = 1: open shell in a spin-orbital basis (h, L
+    block-diagonal over the two spins, Psi_T the occupied spin orbitals, see
+    afq_workloads.spin_orbital_system); every closed-shell factor 2 becomes 1
+    and the exchange term keeps its 1/2."""
+    if spin not in (1, 2):
+        raise ValueError("spin must be 1 or 2")
+    lbar = mean_field_shift(L, psi_t, spin)
     H1 = effective_one_body(h, L, lbar)
     B = half_step_propagator(H1, tau)
     h_half = psi_t.T @ h
     L_half = np.stack([psi_t.T @ L[g] for g in range(L.shape[0])])
     p = Prepared(h, L, float(e_core), psi_t, float(tau), lbar, H1, B,
-                 energy_constant(e_core, lbar), h_half, L_half, 0.0)
+                 energy_constant(e_core, lbar), h_half, L_half, 0.0, spin)
     if e0 is None:
         e0 = local_energy(p, psi_t.astype(complex), psi_t.astype(complex)).real
     p.e0 = float(e0)
@@ -145,11 +154,12 @@ def overlap(psi_t: np.ndarray, phi: np.ndarray):
 # --------------------------------------------------------------------------
 
 def coulomb_vector(p: Prepared, theta: np.ndarray) -> np.ndarray:
-    """ell_g = <Psi_T|Lhat_g|Phi>/<Psi_T|Phi> = 2 tr(Psi_T^T L_g Theta)."""
+    """ell_g = <Psi_T|Lhat_g|Phi>/<Psi_T|Phi> = 2 tr(Psi_T^T L_g Theta)
+    (closed shell; tr(...) for spin orbitals)."""
     G = p.G
     ell = np.empty(G, dtype=complex)
     for g in range(G):
-        ell[g] = 2.0 * np.trace(p.L_half[g] @ theta)
+        ell[g] = p.spin * np.trace(p.L_half[g] @ theta)
     return ell
 
 
@@ -336,16 +346,20 @@ def local_energy(p: Prepared, phi: np.ndarray, theta: np.ndarray) -> complex:
     With Theta = Phi (Psi_T^T Phi)^-1 and T_g = Psi_T^T L_g Theta (N x N),
     Wick's theorem for a closed-shell pair of determinants gives
         E_L = e_core + 2 tr(Psi_T^T h Theta)
-              + (1/2) sum_g (2 tr T_g)^2 - sum_g tr(T_g T_g)."""
-    e1 = 2.0 * np.trace(p.h_half @ theta)
+              + (1/2) sum_g (2 tr T_g)^2 - sum_g tr(T_g T_g),
+    and for a pair of spin-orbital determinants (p.spin = 1)
+        E_L = e_core + tr(Psi_T^T h Theta)
+              + (1/2) sum_g (tr T_g)^2 - (1/2) sum_g tr(T_g T_g)."""
+    s = p.spin
+    e1 = s * np.trace(p.h_half @ theta)
     ej = 0.0 + 0.0j
     ek = 0.0 + 0.0j
     for g in range(p.G):
         T = p.L_half[g] @ theta
         tr = np.trace(T)
-        ej += 0.5 * (2.0 * tr) ** 2
+        ej += 0.5 * (s * tr) ** 2
         ek += np.sum(T * T.T)
-    return complex(p.e_core + e1 + ej - ek)
+    return complex(p.e_core + e1 + ej - 0.5 * s * ek)
 
 
 def energy_window(n_electrons: int, tau: float) -> float:
@@ -493,7 +507,7 @@ def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
     the field integral, so both placements sample the same propagator."""
     if not wk.alive:
         e = local_energy(p, wk.phi, wk.theta)
-        return wk, StepInfo(e, capped_energy(e, p.e0, 2 * p.N, p.tau),
+        return wk, StepInfo(e, capped_energy(e, p.e0, p.spin * p.N, p.tau),
                             0j, 0.0, 0j, 0, np.zeros(p.G, complex))
     if fb_at == FB_HALF:
         if prop != PROP_SPLIT2:
@@ -510,10 +524,12 @@ def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
     if theta is None or not np.all(np.isfinite(theta)) or not np.isfinite(logdet):
         dead = Walker(wk.phi, wk.logdet, wk.theta, 0.0, False)
         e = local_energy(p, dead.phi, dead.theta)
-        return dead, StepInfo(e, capped_energy(e, p.e0, 2 * p.N, p.tau), 0j,
+        return dead, StepInfo(e, capped_energy(e, p.e0, p.spin * p.N, p.tau), 0j,
                               0.0, log_i, int(np.sum(fbar == 0)), f,
                               "frozen" if wk.weight != 0.0 else "")
-    log_ratio = 2.0 * (logdet - wk.logdet) + s_mf
+    # <Psi_T|Phi> = det(Psi_T^T Phi)^spin (both spins share the determinant
+    # in the closed-shell form)
+    log_ratio = p.spin * (logdet - wk.logdet) + s_mf
     e_h = hybrid_energy(p, log_ratio, log_i)
     dtheta = float(log_ratio.imag)
     factor, rule = phaseless_parts(p, e_h, dtheta)
@@ -527,7 +543,7 @@ def walker_step(p: Prepared, wk: Walker, x: np.ndarray, method: int, k: int,
     e = local_energy(p, phi, theta)
     n_capped = int(np.sum(np.abs(f) >= 1.0))
     return (Walker(phi, logdet, theta, weight, True),
-            StepInfo(e, capped_energy(e, p.e0, 2 * p.N, p.tau), e_h, dtheta,
+            StepInfo(e, capped_energy(e, p.e0, p.spin * p.N, p.tau), e_h, dtheta,
                      log_i, n_capped, f, rule))
 
 
@@ -658,13 +674,16 @@ def pop_control_due(step: int, every: int) -> bool:
 # --------------------------------------------------------------------------
 
 def local_energy_gradient(p: Prepared, theta: np.ndarray):
-    """d Re E_L / d h and d Re E_L / d L_g at a fixed walker (and fixed Psi_T).
+    """d Re E_L / d h and d Re E_L / d L_g at a fixed walker (and fixed Psi_T),
+    closed shell (p.spin = 2).
 
     From E_L = e_core + 2 tr(Psi_T^T h Theta) + (1/2) sum_g ell_g^2
     - sum_g tr(T_g T_g):
         dE/dh_pq   = 2 (Psi_T Theta^T)_pq
         dE/dL_g,pq = ell_g 2 (Psi_T Theta^T)_pq - 2 (Psi_T T_g^T Theta^T)_pq
     Gradients are with respect to unconstrained matrix entries; real parts."""
+    if p.spin != 2:
+        raise ValueError("the gradients are written for the closed-shell form")
     P = p.psi_t @ theta.T                       # (M, M) complex
     gh = 2.0 * P.real
     gL = np.empty_like(p.L)
@@ -680,6 +699,8 @@ def coulomb_vector_gradient(p: Prepared, theta: np.ndarray, d_ell: np.ndarray):
     L_g Theta) with respect to the real entries of L_g, contracted with a
     real upstream gradient on Re ell and Im ell packed as complex d_ell:
         grad L_g = Re(d_ell_g) 2 Re(Psi_T Theta^T) + Im(d_ell_g) 2 Im(Psi_T Theta^T)."""
+    if p.spin != 2:
+        raise ValueError("the gradients are written for the closed-shell form")
     P = 2.0 * (p.psi_t @ theta.T)
     return (d_ell.real[:, None, None] * P.real[None]
             + d_ell.imag[:, None, None] * P.imag[None])
