@@ -91,14 +91,32 @@ afq_status afq_init_hamiltonian(afq_ctx* ctx, int64_t M, int64_t n_chol,
                                 int ptr_is_device, int32_t* sys_id);
 
 /* Trial determinant Psi_T (Sec. II.A): M x n_alpha real, orthonormal
- * columns (checked to 1e-10).  n_beta must equal n_alpha (closed shell).
- * Precomputes the mean-field shift Lbar_g (Eq. force_shift), the one-body
- * matrix H1 = h - 1/2 sum_g L_g L_g + sum_g Lbar_g L_g that accompanies the
- * shifted HS transform, its eigendecomposition for the exact half-step
- * exp(-tau H1/2) of Sec. III.B, the half-rotated Psi_T^T h and Psi_T^T L_g,
- * and the trial energy E_L(Psi_T). */
+ * columns (checked to 1e-10), row-major, host or device memory (copied).
+ * Closed shell: n_beta must equal n_alpha, and the alpha and beta blocks of
+ * every walker are equal, so each trace of Eqs. eloc, hyben and force_shift
+ * carries a spin factor 2 (AFQ_EINVAL otherwise, naming
+ * afq_init_trial_spin_orbital).  Precomputes the mean-field shift Lbar_g
+ * (Eq. force_shift), the one-body matrix H1 = h - 1/2 sum_g L_g L_g +
+ * sum_g Lbar_g L_g that accompanies the shifted HS transform, its
+ * eigendecomposition for the exact half-step exp(-tau H1/2) of Sec. III.B,
+ * the half-rotated Psi_T^T h and Psi_T^T L_g, and the trial energy
+ * E_L(Psi_T).  AFQ_ESTATE if the system already has a trial. */
 afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha,
                           int64_t n_beta, const double* psi_t, int ptr_is_device);
+
+/* Open-shell trial (any N_alpha, N_beta, including a UHF determinant): the
+ * system's M basis functions are spin orbitals (for a spatial Hamiltonian
+ * (h, L) of M/2 orbitals, h and every L_g block-diagonal diag(X, X)) and
+ * Psi_T is one M x n_elec determinant of spin orbitals (for (Psi_a, Psi_b)
+ * the block-diagonal diag(Psi_a, Psi_b), n_elec = N_alpha + N_beta).  The
+ * traces of Eqs. eloc, hyben and force_shift then run over one
+ * determinant: spin factor 1.  Everything else, and every other entry point,
+ * is as for afq_init_trial: walkers are M x n_elec, log-overlaps are of the
+ * whole determinant; the two adjoints return AFQ_EINVAL on such a system.
+ * The propagator keeps a walker in the block structure of H1 and L_g, so a
+ * block-diagonal start stays block-diagonal. */
+afq_status afq_init_trial_spin_orbital(afq_ctx* ctx, int32_t sys_id, int64_t n_elec,
+                                       const double* psi_t, int ptr_is_device);
 
 /* Walker store of a system (Eq. wavefun_rep): n_walkers determinants set to
  * phi0 (complex128, n_walkers x M x N) or, if phi0 is NULL, to Psi_T; weights
@@ -252,7 +270,8 @@ afq_status afq_force_bias_adjoint(afq_ctx* ctx, int32_t sys_id, const double* d_
                                   double* grad_L, int ptr_is_device);
 
 /* Read / write the walker store: phi complex128 [W][M][N], weight [W],
- * log_ovlp complex128 [W] (log det(Psi_T^T Phi), one spin), alive int32 [W].
+ * log_ovlp complex128 [W] (log det(Psi_T^T Phi) of the one stored
+ * determinant: one spin block of a closed-shell walker), alive int32 [W].
  * Any output pointer may be NULL.  afq_set_walkers recomputes the Green's
  * functions and the log-overlaps of the given determinants. */
 afq_status afq_get_walkers(afq_ctx* ctx, int32_t sys_id, void* phi, double* weight,

@@ -31,7 +31,7 @@ EXPORTED = (
     "afq_set_walkers", "afq_fill_fields", "afq_get_counters", "afq_profile",
     "afq_profile_read", "afq_sync", "afq_autotune", "afq_get_e0",
     "afq_local_energy_batch_noalloc", "afq_stats_time_average", "afq_stats_kappa",
-    "afq_stats_blocking", "afq_tau_fit",
+    "afq_stats_blocking", "afq_tau_fit", "afq_init_trial_spin_orbital",
 )
 FIT_QUADRATIC, FIT_PURE_SQUARE, FIT_LINEAR = 0, 1, 2
 PHASES = ("fields", "force_bias", "opbuild", "onebody", "exponential", "overlap", "weight", "qr",
@@ -79,6 +79,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "afq_last_error": (ctypes.c_char_p, [P]),
         "afq_init_hamiltonian": (i32, [P, i64, i64, P, P, d, ctypes.c_int, ctypes.POINTER(i32)]),
         "afq_init_trial": (i32, [P, i32, i64, i64, P, ctypes.c_int]),
+        "afq_init_trial_spin_orbital": (i32, [P, i32, i64, P, ctypes.c_int]),
         "afq_init_walkers": (i32, [P, i32, i64, P, ctypes.c_int]),
         "afq_propagate_batch": (i32, [P, ctypes.POINTER(i32), i32, ctypes.POINTER(PropParams)]),
         "afq_local_energy_batch": (i32, [P, i32, i32, P, P, ctypes.c_int]),
@@ -234,6 +235,14 @@ class Context:
         N = psi_t.shape[1]
         self._check(self._lib.afq_init_trial(self._h, sys_id, N, N if n_beta is None else n_beta,
                                              p, dev))
+        self.dims[sys_id]["N"] = N
+
+    def init_trial_spin_orbital(self, sys_id: int, psi_t):
+        """One determinant of spin orbitals (spin factor 1); the system's
+        basis must be spin orbitals."""
+        p, dev, keep = _arg(psi_t, np.float64)
+        N = psi_t.shape[1]
+        self._check(self._lib.afq_init_trial_spin_orbital(self._h, sys_id, N, p, dev))
         self.dims[sys_id]["N"] = N
 
     def init_walkers(self, sys_id: int, n_walkers: int, phi0=None):

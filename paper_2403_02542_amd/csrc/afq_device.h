@@ -776,7 +776,7 @@ AFQ_DEV void exchange_reduce(const TS* Ts, const int* boff_in, const double* con
 template <typename TS, int PITCH, int NBMAX, typename ACC, int RT, int CT, class RowOf>
 AFQ_DEV void exchange_epilogue(ACC (&acc)[RT][CT], RowOf row_of, int mtv, int N, int ga, int wb,
                                int g0, int w0, int G1, TS* Ts, int gpp, double* red,
-                               const double* __restrict__ T0,
+                               const double* __restrict__ T0, double lscale,
                                double* __restrict__ ell_re, double* __restrict__ ell_im,
                                double* __restrict__ ex_re, double* __restrict__ ex_im) {
   static_assert(PITCH >= CT * 16, "pitch");
@@ -837,8 +837,8 @@ AFQ_DEV void exchange_epilogue(ACC (&acc)[RT][CT], RowOf row_of, int mtv, int N,
         const int64_t o = (int64_t)(w0 + wl) * G1 + g0 + gb0 + gl;
         ex_re[o] = s[0];
         ex_im[o] = s[1];
-        ell_re[o] = 2.0 * s[2];
-        ell_im[o] = 2.0 * s[3];
+        ell_re[o] = lscale * s[2];
+        ell_im[o] = lscale * s[3];
       }
       __syncthreads();
     }

@@ -24,6 +24,10 @@ struct E0Dev {
 struct SysDev {
   int M = 0, N = 0, G = 0, W = 0;
   double e_core = 0.0;
+  // spin factor of the traces of one determinant: 2 for a closed-shell
+  // determinant of spatial orbitals (both spin blocks equal), 1 for one
+  // determinant of spin orbitals
+  double spin = 2.0;
   // Hamiltonian
   double* h = nullptr;        // [M][M]
   double* L = nullptr;        // [G][M][M]
@@ -174,6 +178,7 @@ struct XSys {
   double* ex_re;
   double* ex_im;
   int G1, N, K, W, GA, WB, grp, ct;
+  double lscale;   // ell_g = lscale tr T_g (the spin factor)
 };
 
 // Head and exit count of a persistent launch's device work queue (zero
@@ -206,6 +211,7 @@ struct BackSys {
   const double* th_im;
   double e_const;
   int N, M;
+  double spin;
 };
 
 // ------------------------------------------------------------------ launchers

@@ -734,7 +734,7 @@ afq_status get_btable(afq_ctx* ctx, const std::vector<SysDev*>& ss, afq_ctx::BTa
     bs[i] = BackSys{s.psit, s.phn_re, s.phn_im, s.thn_re, s.thn_im, s.logdet_n, s.bad,
                     s.qr_logr, s.alive, s.weight, s.logdet, s.scal, s.e0s,
                     s.counters ? s.counters + 3 : nullptr, s.phi_re, s.phi_im, s.th_re,
-                    s.th_im, s.e_const, s.N, s.M};
+                    s.th_im, s.e_const, s.N, s.M, s.spin};
     put_bytes(key, bs[i]);
     put_bytes(key, s.W);
     if (s.N > max_n) max_n = s.N;
@@ -1038,18 +1038,14 @@ afq_status afq_init_hamiltonian(afq_ctx* ctx, int64_t M, int64_t n_chol, const d
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
 }
 
-afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t n_beta,
-                          const double* psi_t, int ptr_is_device) try {
-  SysDev* sp;
-  TRY(get_sys(ctx, sys_id, &sp));
-  SysDev& s = *sp;
-  if (!psi_t) return fail(ctx, AFQ_EINVAL, "null psi_t");
-  if (n_alpha != n_beta) return fail(ctx, AFQ_EINVAL, "only closed-shell trials (n_alpha == n_beta)");
-  if (n_alpha < 1 || n_alpha > s.M || n_alpha > 80)
-    return fail(ctx, AFQ_EINVAL, "n_alpha must be in [1, min(M, 80)]");
-  if (s.trial_ready) return fail(ctx, AFQ_ESTATE, "trial already set for this system");
-  HIPCHK(hipSetDevice(ctx->device));
-  const int M = s.M, N = (int)n_alpha, G = s.G;
+namespace {
+
+// Trial set-up shared by the closed-shell and the spin-orbital entry points:
+// N orbitals of one determinant, spin factor `spin` (2 or 1).
+afq_status init_trial(afq_ctx* ctx, SysDev& s, int32_t sys_id, int N, double spin,
+                      const double* psi_t, int ptr_is_device) {
+  s.spin = spin;
+  const int M = s.M, G = s.G;
   std::vector<double> psi((size_t)M * N);
   if (ptr_is_device) {
     HIPCHK(hipMemcpyAsync(psi.data(), psi_t, psi.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -1169,6 +1165,38 @@ afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t
   s.e_trial = eh[0];
   s.trial_ready = true;
   return AFQ_OK;
+}
+
+}  // namespace
+
+afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t n_beta,
+                          const double* psi_t, int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  if (!psi_t) return fail(ctx, AFQ_EINVAL, "null psi_t");
+  if (n_alpha != n_beta)
+    return fail(ctx, AFQ_EINVAL,
+                "n_alpha != n_beta: write the system in spin orbitals and use "
+                "afq_init_trial_spin_orbital");
+  if (n_alpha < 1 || n_alpha > sp->M || n_alpha > 80)
+    return fail(ctx, AFQ_EINVAL, "n_alpha must be in [1, min(M, 80)]");
+  if (sp->trial_ready) return fail(ctx, AFQ_ESTATE, "trial already set for this system");
+  HIPCHK(hipSetDevice(ctx->device));
+  return init_trial(ctx, *sp, sys_id, (int)n_alpha, 2.0, psi_t, ptr_is_device);
+} catch (...) {
+  return fail(ctx, AFQ_ENOMEM, "host allocation failed");
+}
+
+afq_status afq_init_trial_spin_orbital(afq_ctx* ctx, int32_t sys_id, int64_t n_elec,
+                                       const double* psi_t, int ptr_is_device) try {
+  SysDev* sp;
+  TRY(get_sys(ctx, sys_id, &sp));
+  if (!psi_t) return fail(ctx, AFQ_EINVAL, "null psi_t");
+  if (n_elec < 1 || n_elec > sp->M || n_elec > 80)
+    return fail(ctx, AFQ_EINVAL, "n_elec must be in [1, min(M, 80)]");
+  if (sp->trial_ready) return fail(ctx, AFQ_ESTATE, "trial already set for this system");
+  HIPCHK(hipSetDevice(ctx->device));
+  return init_trial(ctx, *sp, sys_id, (int)n_elec, 1.0, psi_t, ptr_is_device);
 } catch (...) {
   return fail(ctx, AFQ_ENOMEM, "host allocation failed");
 }
@@ -1671,6 +1699,7 @@ afq_status afq_local_energy_adjoint(afq_ctx* ctx, int32_t sys_id, const double* 
   SysDev& s = *sp;
   if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
   if (!dE_dEL || !grad_h || !grad_L) return fail(ctx, AFQ_EINVAL, "null pointer");
+  if (s.spin != 2.0) return fail(ctx, AFQ_EINVAL, "adjoints are for closed-shell trials only");
   HIPCHK(hipSetDevice(ctx->device));
   const size_t M = s.M, W = s.W, G = s.G;
   double *TH, *Ub, *Db, *Y, *ellt, *dE;
@@ -1704,6 +1733,7 @@ afq_status afq_force_bias_adjoint(afq_ctx* ctx, int32_t sys_id, const double* d_
   SysDev& s = *sp;
   if (!s.W) return fail(ctx, AFQ_ESTATE, "no walkers");
   if (!d_ell || !grad_L) return fail(ctx, AFQ_EINVAL, "null pointer");
+  if (s.spin != 2.0) return fail(ctx, AFQ_EINVAL, "adjoints are for closed-shell trials only");
   HIPCHK(hipSetDevice(ctx->device));
   const size_t M = s.M, W = s.W, G = s.G;
   double *TH, *Ub, *Db, *Y, *ellt, *dl;

@@ -1,10 +1,10 @@
-// The Coulomb vector ell_g = 2 tr T_g over the virtual space (the FP64
-// companion of the BF16-split local energy): with Theta = Psi_T +
-// Psi_perp Theta_v,
-//   ell_g = 2 tr T0_g + 2 sum_(i,k) (Psi_T^T L_g Psi_perp)[i][k] Theta_v[k][i],
+// The Coulomb vector ell_g = s tr T_g over the virtual space (the FP64
+// companion of the BF16-split local energy; s the spin factor, 2 for a
+// closed-shell determinant): with Theta = Psi_T + Psi_perp Theta_v,
+//   ell_g = s tr T0_g + s sum_(i,k) (Psi_T^T L_g Psi_perp)[i][k] Theta_v[k][i],
 // one product [W x N Kv] x [N Kv x G] per plane on the FP64 matrix cores,
 // cut into S slices of whole orbitals (batch entries writing partial sums)
-// and summed in slice order with the trial part 2 tr T0_g.
+// and summed in slice order with the trial part s tr T0_g.
 #include "afq_device.h"
 #include "afq_internal.h"
 
@@ -21,12 +21,13 @@ __global__ void k_sum_slices_t0(const double* __restrict__ part, int S, int W, i
   out[w * G1 + g] = v;
 }
 
-__global__ void k_t0_trace(int G, int N, const double* __restrict__ T0, double* __restrict__ out) {
+__global__ void k_t0_trace(int G, int N, double spin, const double* __restrict__ T0,
+                           double* __restrict__ out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   double t = 0.0;
   for (int i = 0; i < N; ++i) t += T0[(int64_t)g * N * N + (int64_t)i * N + i];
-  out[g] = 2.0 * t;
+  out[g] = spin * t;
 }
 
 }  // namespace
@@ -41,8 +42,8 @@ int coulomb_v_slices(int W, int G, int N, int Kv) {
 }
 
 hipError_t launch_t0_trace(SysDev& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_t0_trace, dim3((s.G + 255) / 256), dim3(256), 0, st, s.G, s.N, s.T0,
-                     s.t0tr);
+  hipLaunchKernelGGL(k_t0_trace, dim3((s.G + 255) / 256), dim3(256), 0, st, s.G, s.N, s.spin,
+                     s.T0, s.t0tr);
   return hipGetLastError();
 }
 
@@ -66,7 +67,7 @@ hipError_t launch_coulomb_v(SysDev& s, const double* thv_re, const double* thv_i
     c.A = planes[pl]; c.sAb = kc; c.sAr = NK; c.sAk = 1; c.sAkb = 0;
     c.B = s.Lov; c.sBb = kc; c.sBc = NK; c.sBk = 1; c.sBkb = 0;
     c.C = part; c.sCb = (int64_t)W * G; c.sCr = G; c.sCc = 1;
-    c.R = W; c.Cn = G; c.K = kc; c.kin = kc; c.batch = S; c.alpha = 2.0; c.beta = 0.0;
+    c.R = W; c.Cn = G; c.K = kc; c.kin = kc; c.batch = S; c.alpha = s.spin; c.beta = 0.0;
     hipError_t e = launch_gemm(c, st);
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)W * G;

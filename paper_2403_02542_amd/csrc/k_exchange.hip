@@ -12,9 +12,11 @@
 // the epilogue adding T0 (real, symmetric),
 // then stages the tile in LDS a few blocks at a time and reduces every
 // N x N block (exchange_epilogue) to
-//   ell_g = 2 tr T_g        (the mixed <Lhat_g>, also the next force bias)
+//   ell_g = s tr T_g        (the mixed <Lhat_g>, also the next force bias)
 //   X_g   = tr(T_g T_g)     (exchange term)
-// The h block gives ell_G = 2 tr(Psi_T^T h Theta), the one-body energy.
+// with s the spin factor (2 for a closed-shell determinant of spatial
+// orbitals, 1 for spin orbitals).  The h block gives ell_G = s tr(Psi_T^T h
+// Theta), the one-body energy.
 //
 // Main loop: the eight waves split the 16-row MFMA tiles of the tile rows
 // evenly (ceil(TR / 8) each) and all hold every column tile, so a 250-row
@@ -163,7 +165,7 @@ __device__ __forceinline__ void exchange_tile_run(const XSys& p, int gt, int wt,
   // ---- epilogue: the rows of `grp` g-blocks at a time staged in LDS
   exchange_epilogue<double, CT * 16 + 2, 4>(
       acc, [&](int i, int e) { return (rt0 + i) * 16 + 4 * e + lk; }, mtv, N, ga, wb, g0, w0, G1,
-      smem, grp, smem + X_LDS - X_RED, p.T0, ell_re, ell_im, ex_re, ex_im);
+      smem, grp, smem + X_LDS - X_RED, p.T0, p.lscale, ell_re, ell_im, ex_re, ex_im);
 }
 
 template <int CT>
@@ -242,7 +244,7 @@ hipError_t exchange_setup(const SysDev& s, int W, const double* thv_re, const do
   if (grp > 32) grp = 32;
   if (grp < 1) return hipErrorInvalidValue;
   *p = XSys{s.Lov, s.T0, thv_re, thv_im, ell_re, ell_im, ex_re, ex_im, G1, N, s.Kv, W, GA, WB,
-            grp, ct};
+            grp, ct, s.spin};
   *n_gt = (G1 + GA - 1) / GA;
   *n_wt = (W + WB - 1) / WB;
   return hipSuccess;
@@ -366,7 +368,8 @@ void exchange_candidates(int N, std::vector<int2>& out) {
 }
 
 // ------------------------------------------------------------ Coulomb vector only
-// ell_g^w = 2 tr T_g^w = 2 sum_(i,p) (Psi_T^T L_g)[i][p] Theta^w[p][i]: one
+// ell_g^w = s tr T_g^w = s sum_(i,p) (Psi_T^T L_g)[i][p] Theta^w[p][i] (s the
+// spin factor): one
 // product [W x NM] x [NM x G] per plane, for the steps that do not measure the
 // energy (the force bias needs ell every step; the exchange term only when the
 // energy is measured).  K = NM is cut into S slices (batch entries writing
@@ -407,7 +410,7 @@ hipError_t launch_coulomb(SysDev& s, const double* th_re, const double* th_im, d
     c.A = planes[pl]; c.sAb = kc; c.sAr = NM; c.sAk = 1; c.sAkb = 0;
     c.B = s.Lx; c.sBb = kc; c.sBc = NM; c.sBk = 1; c.sBkb = 0;
     c.C = part; c.sCb = (int64_t)W * G; c.sCr = G; c.sCc = 1;
-    c.R = W; c.Cn = G; c.K = kc; c.kin = kc; c.batch = S; c.alpha = 2.0; c.beta = 0.0;
+    c.R = W; c.Cn = G; c.K = kc; c.kin = kc; c.batch = S; c.alpha = s.spin; c.beta = 0.0;
     hipError_t e = launch_gemm(c, st);
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)W * G;

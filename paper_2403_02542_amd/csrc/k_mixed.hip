@@ -101,7 +101,8 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
                                                      double* __restrict__ ell_im,
                                                      double* __restrict__ ex_re,
                                                      double* __restrict__ ex_im,
-                                                     const double* __restrict__ T0) {
+                                                     const double* __restrict__ T0,
+                                                     double lscale) {
   extern __shared__ double smem[];
   unsigned short* lds = (unsigned short*)smem;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(MT_) void k_exchange_mx(int G1, int N, int Kp, int 
   // precision)
   exchange_epilogue<float, CT * 16 + 2, 6>(
       acc, [&](int i, int e) { return (rt0 + i) * 16 + (lane >> 4) * 4 + e; }, mtv, N, ga, wb, g0,
-      w0, G1, (float*)smem, grp, smem + red_off, T0, ell_re, ell_im, ex_re, ex_im);
+      w0, G1, (float*)smem, grp, smem + red_off, T0, lscale, ell_re, ell_im, ex_re, ex_im);
 }
 
 void exchange_mx_tile(int N, int& GA, int& WB) {
@@ -305,7 +306,7 @@ hipError_t launch_mx(SysDev& s, int W, const unsigned short* tb, int64_t tb_ps, 
   }
   hipLaunchKernelGGL((k_exchange_mx<CT, P>), dim3(grid), dim3(MT_), lds_doubles * 8, st, G1, N,
                      s.Kp, W, GA, WB, n_gt, n_wt, grp, red_off, s.Lxb, s.Lxb_ps, tb, tb_ps, ell_re, ell_im,
-                     ex_re, ex_im, s.T0);
+                     ex_re, ex_im, s.T0, s.spin);
   return hipGetLastError();
 }
 

@@ -67,8 +67,9 @@ __global__ void k_fields(uint64_t seed, uint64_t sid, uint64_t step, int W, int 
 
 // ---------------------------------------------------------------- set-up
 
-// Lbar_g = 2 tr(Psi_T^T L_g Psi_T) = 2 sum_{i,p} (Psi_T^T L_g)[i][p] Psi_T[p][i]
-__global__ __launch_bounds__(256) void k_lbar(int N, int M, const double* __restrict__ Lx,
+// Lbar_g = s tr(Psi_T^T L_g Psi_T) = s sum_{i,p} (Psi_T^T L_g)[i][p] Psi_T[p][i],
+// s the spin factor
+__global__ __launch_bounds__(256) void k_lbar(int N, int M, double spin, const double* __restrict__ Lx,
                                               const double* __restrict__ psit,
                                               double* __restrict__ lbar) {
   __shared__ double red[4];
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_lbar(int N, int M, const double* __rest
   double s = 0.0;
   for (int e = threadIdx.x; e < N * M; e += 256) s += X[e] * psit[e];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) lbar[g] = 2.0 * s;
+  if (threadIdx.x == 0) lbar[g] = spin * s;
 }
 
 // out[pq] += alpha sum_g coef[g] L[g][pq]
@@ -372,11 +373,13 @@ __global__ __launch_bounds__(256) void k_overlap(int N, int M, const double* __r
 }
 
 // ---------------------------------------------------------------- weights
-// log R = 2 (logdet_new - logdet_old) + s_mf;  E_H = -(log R + log I)/tau + e_const;
+// log R = s (logdet_new - logdet_old) + s_mf (s the spin factor: the
+// log-overlap is kept per determinant);  E_H = -(log R + log I)/tau + e_const;
 // dtheta = Im log R;  m = exp(-tau (Re E_H - E0)), m >= 10 -> 0;
 // W <- W m max(0, cos dtheta).  A walker whose new state is non-finite is
 // frozen (alive = 0, W = 0); frozen walkers are never updated again.
-AFQ_DEV void weight_one(int w, double tau, const E0Dev* __restrict__ e0s, double e_const,
+AFQ_DEV void weight_one(int w, double tau, double spin, const E0Dev* __restrict__ e0s,
+                        double e_const,
                         const double* __restrict__ logdet_n, double* __restrict__ logdet,
                         const double* __restrict__ scal, const int* __restrict__ bad,
                         const double* __restrict__ qr_logr, int* __restrict__ alive,
@@ -389,8 +392,8 @@ AFQ_DEV void weight_one(int w, double tau, const E0Dev* __restrict__ e0s, double
     if (nfrozen) atomicAdd(nfrozen, 1);
     return;
   }
-  const double lr = 2.0 * (logdet_n[w * 2] - logdet[w * 2]) + scal[w * 4 + 2];
-  const double li = 2.0 * (logdet_n[w * 2 + 1] - logdet[w * 2 + 1]) + scal[w * 4 + 3];
+  const double lr = spin * (logdet_n[w * 2] - logdet[w * 2]) + scal[w * 4 + 2];
+  const double li = spin * (logdet_n[w * 2 + 1] - logdet[w * 2 + 1]) + scal[w * 4 + 3];
   const double eh = -(lr + scal[w * 4 + 0]) / tau + e_const;
   double m = exp(-tau * (eh - e0));
   if (!(m < 10.0)) m = 0.0;
@@ -401,14 +404,16 @@ AFQ_DEV void weight_one(int w, double tau, const E0Dev* __restrict__ e0s, double
   logdet[w * 2 + 1] = logdet_n[w * 2 + 1];
 }
 
-__global__ void k_weight(int W, double tau, const E0Dev* __restrict__ e0s, double e_const,
+__global__ void k_weight(int W, double tau, double spin, const E0Dev* __restrict__ e0s,
+                         double e_const,
                          const double* __restrict__ logdet_n, double* __restrict__ logdet,
                          const double* __restrict__ scal, const int* __restrict__ bad,
                          const double* __restrict__ qr_logr, int* __restrict__ alive,
                          double* __restrict__ weight, int* __restrict__ nfrozen) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
-  weight_one(w, tau, e0s, e_const, logdet_n, logdet, scal, bad, qr_logr, alive, weight, nfrozen);
+  weight_one(w, tau, spin, e0s, e_const, logdet_n, logdet, scal, bad, qr_logr, alive, weight,
+             nfrozen);
 }
 
 // ---------------------------------------------------------------- QR
@@ -630,7 +635,7 @@ __global__ __launch_bounds__(256) void k_back_queue(const BackSys* __restrict__ 
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      weight_one(w, tau, S.e0s, S.e_const, S.logdet_n, S.logdet, S.scal, S.bad,
+      weight_one(w, tau, S.spin, S.e0s, S.e_const, S.logdet_n, S.logdet, S.scal, S.bad,
                  due ? S.qr_logr : nullptr, S.alive, S.weight, S.nfrozen);
       run = !S.alive[w];
     }
@@ -644,9 +649,11 @@ __global__ __launch_bounds__(256) void k_back_queue(const BackSys* __restrict__ 
 }
 
 // ---------------------------------------------------------------- energy
-// E_L = e_core + E1 + 1/2 sum_g ell_g^2 - sum_g X_g,  E1 = ell_G (the h block),
-// X_g = tr(T_g T_g).  Capped: clamp(Re E_L, E0 -+ dE) if dE > 0.
-__global__ __launch_bounds__(256) void k_energy(int G, int G1, double e_core,
+// E_L = e_core + E1 + 1/2 sum_g ell_g^2 - (s / 2) sum_g X_g,  E1 = ell_G (the
+// h block), X_g = tr(T_g T_g), s the spin factor (each spin block of a
+// closed-shell determinant adds X_g / 2).  Capped: clamp(Re E_L, E0 -+ dE)
+// if dE > 0.
+__global__ __launch_bounds__(256) void k_energy(int G, int G1, double e_core, double xs,
                                                 const double* __restrict__ ell_re,
                                                 const double* __restrict__ ell_im,
                                                 const double* __restrict__ ex_re,
@@ -662,8 +669,8 @@ __global__ __launch_bounds__(256) void k_energy(int G, int G1, double e_core,
   const double* xi = ex_im + (int64_t)w * G1;
   double sr = 0.0, si = 0.0;
   for (int g = threadIdx.x; g < G; g += 256) {
-    sr += 0.5 * (lr[g] * lr[g] - li[g] * li[g]) - xr[g];
-    si += lr[g] * li[g] - xi[g];
+    sr += 0.5 * (lr[g] * lr[g] - li[g] * li[g]) - xs * xr[g];
+    si += lr[g] * li[g] - xs * xi[g];
   }
   sr = block_sum(sr, red);
   si = block_sum(si, red);
@@ -948,7 +955,8 @@ hipError_t launch_call_advance(CallState* cs, int n, hipStream_t st) {
 }
 
 hipError_t launch_lbar(const SysDev& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_lbar, dim3(s.G), dim3(256), 0, st, s.N, s.M, s.Lx, s.psit, s.lbar);
+  hipLaunchKernelGGL(k_lbar, dim3(s.G), dim3(256), 0, st, s.N, s.M, s.spin, s.Lx, s.psit,
+                     s.lbar);
   return hipGetLastError();
 }
 
@@ -981,7 +989,8 @@ hipError_t launch_overlap(SysDev& s, int W, const double* ph_re, const double* p
 }
 
 hipError_t launch_weight(SysDev& s, double tau, const double* qr_logr, hipStream_t st) {
-  hipLaunchKernelGGL(k_weight, dim3(nblk(s.W, 256)), dim3(256), 0, st, s.W, tau, s.e0s, s.e_const,
+  hipLaunchKernelGGL(k_weight, dim3(nblk(s.W, 256)), dim3(256), 0, st, s.W, tau, s.spin, s.e0s,
+                     s.e_const,
                      s.logdet_n, s.logdet, s.scal, s.bad, qr_logr, s.alive, s.weight,
                      s.counters ? s.counters + 3 : nullptr);
   return hipGetLastError();
@@ -1050,10 +1059,11 @@ hipError_t launch_energy(SysDev& s, int W, const double* ell_re, const double* e
                          const E0Dev* e0s, double tau, hipStream_t st) {
   double dE = 0.0;
   if (tau > 0.0) {
-    const double ne = 2.0 * s.N;
+    const double ne = s.spin * s.N;   // electrons
     dE = 0.5 * sqrt(ne / tau) + sqrt(ne * tau);
   }
-  hipLaunchKernelGGL(k_energy, dim3(W), dim3(256), 0, st, s.G, s.G + 1, s.e_core, ell_re, ell_im,
+  hipLaunchKernelGGL(k_energy, dim3(W), dim3(256), 0, st, s.G, s.G + 1, s.e_core, 0.5 * s.spin,
+                     ell_re, ell_im,
                      ex_re, ex_im, eloc, ecap, e0s, dE);
   return hipGetLastError();
 }

@@ -51,9 +51,10 @@ def wrap(x):
 class Case:
     """One system on both sides."""
 
-    def __init__(self, h, L, psi, e_core=0.0):
+    def __init__(self, h, L, psi, e_core=0.0, spin=2):
         self.h, self.L, self.psi, self.e_core = h, L, psi, e_core
         self.M, self.N, self.G = h.shape[0], psi.shape[1], L.shape[0]
+        self.spin = spin   # 1: (h, L, psi) in spin orbitals, one determinant
 
     @classmethod
     def from_config(cls, name):
@@ -69,12 +70,15 @@ class Case:
 
     def gpu(self, ctx, n_walkers, phi0=None):
         sid = ctx.init_hamiltonian(self.h, self.L, self.e_core)
-        ctx.init_trial(sid, self.psi)
+        if self.spin == 1:
+            ctx.init_trial_spin_orbital(sid, self.psi)
+        else:
+            ctx.init_trial(sid, self.psi)
         ctx.init_walkers(sid, n_walkers, phi0)
         return sid
 
     def oracle(self, tau):
-        return O.prepare(self.h, self.L, self.e_core, self.psi, tau)
+        return O.prepare(self.h, self.L, self.e_core, self.psi, tau, spin=self.spin)
 
 
 def flags_from_info(p, info, weight_factor_ok=True):
@@ -88,7 +92,7 @@ def flags_from_info(p, info, weight_factor_ok=True):
         arg = -p.tau * (info.e_hybrid.real - p.e0)
         if abs(arg - math.log(10.0)) < NEAR:
             flag = True
-    d = O.energy_window(2 * p.N, p.tau)
+    d = O.energy_window(p.spin * p.N, p.tau)
     if min(abs(info.e_loc.real - (p.e0 - d)), abs(info.e_loc.real - (p.e0 + d))) < NEAR:
         flag = True
     return flag
