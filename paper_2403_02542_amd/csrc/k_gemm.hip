@@ -208,103 +208,167 @@ __global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int M,
 
 // ------------------------------------------------------------ A^w psi
 // For walker w and orbitals j < N: out[j][p] = sum_q A^w[p][q] v[j][q]
-// (complex).  Real form: rows r = (plane, j), K = (q, plane') of length 2M:
-//   row (re, j): [ v_re[j][q],  -v_im[j][q] ],   row (im, j): [ v_im, v_re ]
-//   col p:       [ A_re[p][q],   A_im[p][q] ]
+// (complex).  Real form: rows r = (plane, j), r < 2N, and K = (plane', q)
+// in two halves of M:
+//   half 0 (A_re): row (re, j) takes v_re[j][q], row (im, j) takes v_im[j][q],
+//   half 1 (A_im): row (re, j) takes -v_im[j][q], row (im, j) takes v_re[j][q].
 // mode 0: out = A v.   mode 1 (Taylor term n): out = A v / n and sum += out.
 // mode 2 (Chebyshev T_1): out = A v and sum += c out (c = inv_n).
 // mode 3 (Chebyshev T_n): out = 2 A v - out (out holds T_{n-2} on entry, v
 // is T_{n-1}) and sum += c out.
+//
+// A workgroup of MV_W waves covers up to MV_W column tiles (16 values of p
+// each) of one walker, one per wave, and all TR = ceil(2N / 16) row tiles.
+// Each wave is the only reader of its 16 operator rows, so it loads them
+// straight from global memory into its MFMA B fragments (lane (lr, lk) holds
+// A[p0 + lr][q0 + 4 s + lk] for k-step s), the next chunk's while the current
+// one runs; the orbital rows, read by every wave, go through two LDS stages.
+// Each half of K runs in chunks of MV_BK with the last chunk padded with
+// zeros, so the products accumulate in the groups of four consecutive q of a
+// plain ordered sum.  Signs are applied when a chunk is staged, after the
+// MFMAs that hide its loads.  (The BF16-split product is k_matvec_mx.)
+constexpr int MV_W = 8;          // waves (column tiles) per workgroup
+constexpr int MV_BK = 32;
+constexpr int MV_LDK = MV_BK + 1;
 
-// Eight waves: two rows of waves split the 2N rows (RT = ceil(TR / 2) row
-// tiles each) and four columns of waves hold up to two column tiles each;
-// K runs in chunks of 32 so that each fetch from HBM covers 8 MFMA k-steps.
-// Seven row tiles (N = 49..56) would leave one of the eight tiles of two
-// wave rows empty, so there one row of eight waves holds all seven row tiles
-// and one column tile each.  (The BF16-split product is k_matvec_mx.)
-template <int RT>
-struct MvCfg {
-  static constexpr bool ONE_ROW = RT == 7;
-  static constexpr int WR = ONE_ROW ? 1 : 2, WC = ONE_ROW ? 8 : 4;
-  static constexpr int CT = ONE_ROW ? 1 : 2, BK = 32;
-  static constexpr int NT = 64 * WR * WC;
-};
+template <int TR>
+constexpr size_t matvec_lds_bytes() {
+  return (size_t)2 * TR * 16 * MV_LDK * sizeof(double);
+}
 
-template <int RT>
-__global__ __launch_bounds__((MvCfg<RT>::NT)) void k_matvec(int W, int N, int M, VecRef v,
-                                                         const double* __restrict__ A_re,
-                                                         const double* __restrict__ A_im, VecOut o,
-                                                         int mode, double inv_n, VecOut sum,
-                                                         int n_ct) {
+template <int TR>
+__global__ __launch_bounds__(MV_W * 64) void k_matvec(int W, int N, int M, VecRef v,
+                                                      const double* __restrict__ A_re,
+                                                      const double* __restrict__ A_im,
+                                                      VecOut o, int mode, double inv_n,
+                                                      VecOut sum, int n_ct) {
+  constexpr int NT = MV_W * 64;
+  constexpr int ROWS = TR * 16;
+  constexpr int RSTEP = NT / MV_BK;                       // staged rows per pass
+  constexpr int PF = (ROWS + RSTEP - 1) / RSTEP;          // staged elements per thread
+  constexpr int STAGE = ROWS * MV_LDK;
   extern __shared__ double smem[];
   int w, ct;
   if (!xcd_swizzle(blockIdx.x, n_ct, W, w, ct)) return;
-  // balanced column blocks: n_ct blocks over ceil(M/16) tiles
-  const int TCt = (M + 15) / 16;
-  const int tpb = (TCt + n_ct - 1) / n_ct;
-  const int c0 = ct * tpb * 16;
-  if (c0 >= M) return;
-  const int nc = min(tpb * 16, M - c0);
-  const int nr = 2 * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int TC = (M + 15) / 16;
+  const int tpb = (TC + n_ct - 1) / n_ct;   // column tiles of this block (<= MV_W)
+  const int tile = ct * tpb + wave;
+  const bool active = wave < tpb && tile < TC;
+  const int p = tile * 16 + lr;
+  const bool p_ok = active && p < M;
+  const int64_t MM = (int64_t)M * M;
+  const double* Ar = A_re + (int64_t)w * MM + (int64_t)(p_ok ? p : 0) * M;
+  const double* Ai = A_im + (int64_t)w * MM + (int64_t)(p_ok ? p : 0) * M;
   const double* vre = v.re + (int64_t)w * v.sw;
   const double* vim = v.im + (int64_t)w * v.sw;
-  const int64_t MM = (int64_t)M * M;
-  const double* Are = A_re + (int64_t)w * MM;
-  const double* Aim = A_im + (int64_t)w * MM;
-  auto ga = [&](int r, int k) {
-    const bool im_row = r >= N;
-    const int j = im_row ? r - N : r;
-    if (k < M) return im_row ? vim[j * v.sj + k] : vre[j * v.sj + k];
-    const int q = k - M;
-    return im_row ? vre[j * v.sj + q] : -vim[j * v.sj + q];
+  const int nr = 2 * N;
+  const int sk = tid % MV_BK, srow0 = tid / MV_BK;
+  const int nch = (M + MV_BK - 1) / MV_BK, nchunk = 2 * nch;
+
+  double pv[PF], bn[8], bc[8];
+  auto fetch = [&](int c) {
+    const int h = c >= nch;
+    const int q0 = (h ? c - nch : c) * MV_BK;
+    const double* Ah = h ? Ai : Ar;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int q = q0 + 4 * s + lk;
+      bn[s] = (p_ok && q < M) ? Ah[q] : 0.0;
+    }
+    const int q = q0 + sk;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int r = srow0 + i * RSTEP;
+      double x = 0.0;
+      if (r < nr && r < ROWS && q < M) {
+        const bool im_row = r >= N;
+        const int j = im_row ? r - N : r;
+        const double* src = (im_row != (h != 0)) ? vim : vre;
+        x = src[(int64_t)j * v.sj + q];
+      }
+      pv[i] = x;
+    }
   };
-  auto gb = [&](int c, int k) {
-    const int64_t p = c0 + c;
-    return k < M ? Are[p * M + k] : Aim[p * M + (k - M)];
+  auto store = [&](double* S, int c) {
+    const int h = c >= nch;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int r = srow0 + i * RSTEP;
+      if (r < ROWS) S[r * MV_LDK + sk] = (h && r < N) ? -pv[i] : pv[i];
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) bc[s] = bn[s];
   };
-  using C = MvCfg<RT>;
-  pipe_run<C::WR, C::WC, RT, C::CT, 0, false, false, C::BK>(
-      2 * M, nr, nc, ga, gb, smem, [&](int r, int c, double val) {
-        if (r < nr && c < nc) {
-          const bool im_row = r >= N;
-          const int j = im_row ? r - N : r;
-          const int64_t off = (int64_t)w * o.sw + (int64_t)j * o.sj + c0 + c;
-          if (mode == 3) val = 2.0 * val - (im_row ? o.im[off] : o.re[off]);
-          if (mode >= 1) {
-            const double add = mode == 1 ? (val *= inv_n) : inv_n * val;
-            const int64_t soff = (int64_t)w * sum.sw + (int64_t)j * sum.sj + c0 + c;
-            if (im_row) sum.im[soff] += add;
-            else sum.re[soff] += add;
-          }
-          if (im_row) o.im[off] = val;
-          else o.re[off] = val;
-        }
-      });
+
+  d4_t acc[TR];
+#pragma unroll
+  for (int i = 0; i < TR; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  store(smem, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const double* As = smem + (c & 1) * STAGE;
+    const bool more = c + 1 < nchunk;
+    if (more) fetch(c + 1);
+    if (active) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        double a[TR];
+#pragma unroll
+        for (int i = 0; i < TR; ++i) a[i] = As[(i * 16 + lr) * MV_LDK + 4 * s + lk];
+#pragma unroll
+        for (int i = 0; i < TR; ++i) acc[i] = mfma_f64(a[i], bc[s], acc[i]);
+      }
+    }
+    if (more) store(smem + ((c + 1) & 1) * STAGE, c + 1);
+    __syncthreads();
+  }
+  if (!p_ok) return;
+  // accumulator element e of tile i: row i 16 + 4 e + lk, column p
+#pragma unroll
+  for (int i = 0; i < TR; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = i * 16 + 4 * e + lk;
+      if (r >= nr) continue;
+      const bool im_row = r >= N;
+      const int j = im_row ? r - N : r;
+      double val = acc[i][e];
+      const int64_t off = (int64_t)w * o.sw + (int64_t)j * o.sj + p;
+      if (mode == 3) val = 2.0 * val - (im_row ? o.im[off] : o.re[off]);
+      if (mode >= 1) {
+        const double add = mode == 1 ? (val *= inv_n) : inv_n * val;
+        const int64_t soff = (int64_t)w * sum.sw + (int64_t)j * sum.sj + p;
+        if (im_row) sum.im[soff] += add;
+        else sum.re[soff] += add;
+      }
+      if (im_row) o.im[off] = val;
+      else o.re[off] = val;
+    }
 }
 
 int matvec_col_blocks(int M) {
   const int TC = (M + 15) / 16;
-  const int per = MvCfg<4>::WC * MvCfg<4>::CT;   // the same for every shape
-  return (TC + per - 1) / per;
+  return (TC + MV_W - 1) / MV_W;
 }
-static_assert(MvCfg<4>::WC * MvCfg<4>::CT == MvCfg<7>::WC * MvCfg<7>::CT, "column blocks");
 
-template <int RT>
-hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
+template <int TR>
+hipError_t matvec_tr(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                      hipStream_t st) {
-  using C = MvCfg<RT>;
-  constexpr size_t lds = pipe_lds_bytes<C::WR, C::WC, RT, C::CT, 0, C::BK>();
+  constexpr size_t lds = matvec_lds_bytes<TR>();
   static bool lds_ok = false;
   if (!lds_ok) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<RT>,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_matvec<TR>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     lds_ok = true;
   }
   // a tuned count below the minimum would leave column tiles out
   const int n_ct = max(s.mv_ct, matvec_col_blocks(s.M));
-  hipLaunchKernelGGL((k_matvec<RT>), dim3(xcd_grid(s.W, n_ct)), dim3(C::NT), lds, st, s.W, s.N,
-                     s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
+  hipLaunchKernelGGL((k_matvec<TR>), dim3(xcd_grid(s.W, n_ct)), dim3(MV_W * 64), lds, st, s.W,
+                     s.N, s.M, v, s.A_re, s.A_im, o, mode, inv_n, sum, n_ct);
   return hipGetLastError();
 }
 
@@ -312,12 +376,19 @@ hipError_t matvec_rt(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecO
 hipError_t run_matvec(SysDev& s, VecRef v, VecOut o, int mode, double inv_n, VecOut sum,
                       hipStream_t st) {
   if (s.op_pieces > 0) return launch_matvec_mx(s, v, o, mode, inv_n, sum, st);
-  const int TR = (2 * s.N + 15) / 16;
-  if (TR <= 6) return matvec_rt<3>(s, v, o, mode, inv_n, sum, st);
-  if (TR == 7) return matvec_rt<7>(s, v, o, mode, inv_n, sum, st);
-  if (TR <= 8) return matvec_rt<4>(s, v, o, mode, inv_n, sum, st);
-  if (TR <= 10) return matvec_rt<5>(s, v, o, mode, inv_n, sum, st);
-  return hipErrorInvalidValue;
+  switch ((2 * s.N + 15) / 16) {
+    case 1: return matvec_tr<1>(s, v, o, mode, inv_n, sum, st);
+    case 2: return matvec_tr<2>(s, v, o, mode, inv_n, sum, st);
+    case 3: return matvec_tr<3>(s, v, o, mode, inv_n, sum, st);
+    case 4: return matvec_tr<4>(s, v, o, mode, inv_n, sum, st);
+    case 5: return matvec_tr<5>(s, v, o, mode, inv_n, sum, st);
+    case 6: return matvec_tr<6>(s, v, o, mode, inv_n, sum, st);
+    case 7: return matvec_tr<7>(s, v, o, mode, inv_n, sum, st);
+    case 8: return matvec_tr<8>(s, v, o, mode, inv_n, sum, st);
+    case 9: return matvec_tr<9>(s, v, o, mode, inv_n, sum, st);
+    case 10: return matvec_tr<10>(s, v, o, mode, inv_n, sum, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ------------------------------------------------------------ Krylov pieces

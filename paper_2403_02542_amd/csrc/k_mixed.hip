@@ -609,7 +609,9 @@ __global__ __launch_bounds__(MT_) void k_matvec_mx(int W, int N, int M, int Kq, 
     if (k < M) return im_row ? vim[j * v.sj + k] : vre[j * v.sj + k];
     const int q = k - M;
     if (q >= M) return 0.0;
-    return im_row ? vre[j * v.sj + q] : -vim[j * v.sj + q];
+    // -v_im of the real rows: the sign is applied in store_b, so that no
+    // prefetch is waited for before the chunk's MFMAs
+    return im_row ? vre[j * v.sj + q] : vim[j * v.sj + q];
   };
   double pf[PFU][4];
   auto fetch_b = [&](int k0) {
@@ -621,13 +623,18 @@ __global__ __launch_bounds__(MT_) void k_matvec_mx(int W, int N, int M, int Kq, 
       for (int t = 0; t < 4; ++t) pf[i][t] = (u < UNITS && c < nc) ? vget(c, k + t) : 0.0;
     }
   };
-  auto store_b = [&](unsigned short* S) {
+  auto store_b = [&](unsigned short* S, int k0) {
 #pragma unroll
     for (int i = 0; i < PFU; ++i) {
       const int u = tid + i * MT_;
       if (u < UNITS) {
         const int c = u >> 3, k = (u & 7) * 4;
         double x[4] = {pf[i][0], pf[i][1], pf[i][2], pf[i][3]};
+        if (c < N) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (k0 + k + t >= M) x[t] = -x[t];
+        }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           unsigned short b[4];
@@ -657,7 +664,7 @@ __global__ __launch_bounds__(MT_) void k_matvec_mx(int W, int N, int M, int Kq, 
   const int nchunk = Kq / M_KC;
   fetch_a(0, afr);
   fetch_b(0);
-  store_b(lds);
+  store_b(lds, 0);
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
     const unsigned short* Bs = lds + (ch & 1) * BSTAGE;
@@ -691,7 +698,7 @@ __global__ __launch_bounds__(MT_) void k_matvec_mx(int W, int N, int M, int Kq, 
       }
     }
     if (more) {
-      store_b(lds + ((ch + 1) & 1) * BSTAGE);
+      store_b(lds + ((ch + 1) & 1) * BSTAGE, (ch + 1) * M_KC);
 #pragma unroll
       for (int i = 0; i < RT; ++i)
 #pragma unroll
