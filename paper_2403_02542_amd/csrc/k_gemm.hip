@@ -227,7 +227,7 @@ __global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int M,
 // zeros, so the products accumulate in the groups of four consecutive q of a
 // plain ordered sum.  Signs are applied when a chunk is staged, after the
 // MFMAs that hide its loads.  (The BF16-split product is k_matvec_mx.)
-constexpr int MV_W = 8;          // waves (column tiles) per workgroup
+constexpr int MV_W = 4;          // waves (column tiles) per workgroup
 constexpr int MV_BK = 32;
 constexpr int MV_LDK = MV_BK + 1;
 
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(MV_W * 64) void k_matvec(int W, int N, int M, VecRe
   const int nch = (M + MV_BK - 1) / MV_BK, nchunk = 2 * nch;
 
   double pv[PF], bn[8], bc[8];
-  auto fetch = [&](int c) {
+  auto fetch_b = [&](int c) {
     const int h = c >= nch;
     const int q0 = (h ? c - nch : c) * MV_BK;
     const double* Ah = h ? Ai : Ar;
@@ -277,7 +277,10 @@ __global__ __launch_bounds__(MV_W * 64) void k_matvec(int W, int N, int M, VecRe
       const int q = q0 + 4 * s + lk;
       bn[s] = (p_ok && q < M) ? Ah[q] : 0.0;
     }
-    const int q = q0 + sk;
+  };
+  auto fetch_v = [&](int c) {
+    const int h = c >= nch;
+    const int q = (h ? c - nch : c) * MV_BK + sk;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int r = srow0 + i * RSTEP;
@@ -305,14 +308,15 @@ __global__ __launch_bounds__(MV_W * 64) void k_matvec(int W, int N, int M, VecRe
   d4_t acc[TR];
 #pragma unroll
   for (int i = 0; i < TR; ++i) acc[i] = d4_t{0.0, 0.0, 0.0, 0.0};
-  fetch(0);
+  fetch_b(0);
+  fetch_v(0);
   store(smem, 0);
   __syncthreads();
   for (int c = 0; c < nchunk; ++c) {
     const double* As = smem + (c & 1) * STAGE;
     const bool more = c + 1 < nchunk;
-    if (more) fetch(c + 1);
     if (active) {
+      // the next chunk's loads are issued between the MFMAs of this one
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         double a[TR];
@@ -320,7 +324,13 @@ __global__ __launch_bounds__(MV_W * 64) void k_matvec(int W, int N, int M, VecRe
         for (int i = 0; i < TR; ++i) a[i] = As[(i * 16 + lr) * MV_LDK + 4 * s + lk];
 #pragma unroll
         for (int i = 0; i < TR; ++i) acc[i] = mfma_f64(a[i], bc[s], acc[i]);
+        if (s == 0 && more) fetch_b(c + 1);
+        if (s == 4 && more) fetch_v(c + 1);
+        __builtin_amdgcn_sched_barrier(0);
       }
+    } else if (more) {
+      fetch_b(c + 1);
+      fetch_v(c + 1);
     }
     if (more) store(smem + ((c + 1) & 1) * STAGE, c + 1);
     __syncthreads();
