@@ -161,14 +161,18 @@ __global__ __launch_bounds__(OBP::NT) void k_onebody(int WN, int M, int n_ct,
 // the column blocks of (p, q) that hold an element on or above the diagonal
 // are formed (the packed triangle, M(M+1)/2 of the M^2 columns, padded to
 // whole blocks); each element with q >= p is written to A[p][q] and A[q][p].
+// Row tiles of 128 (RT = 2) or, from 2W = 512 rows on, of 256 (RT = 4: twice
+// the MFMAs per staged operand and half the reads of L per column block).
 
+template <int RT_>
 struct OpTile {
-  static constexpr int WR = 4, WC = 2, RT = 2, CT = 4;
+  static constexpr int WR = 4, WC = 2, RT = RT_, CT = 4;
   static constexpr int ROWS = WR * RT * 16, COLS = WC * CT * 16, NT = WR * WC * 64;
 };
-static_assert(OpTile::COLS == kOpRowsFP64 * 16, "a column tile is one 8 x 16 block of (p, q)");
+static_assert(OpTile<2>::COLS == kOpRowsFP64 * 16, "a column tile is one 8 x 16 block of (p, q)");
 
-__global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int M,
+template <int RT_>
+__global__ __launch_bounds__(OpTile<RT_>::NT) void k_opbuild(int W, int G, int M,
                                                      const double* __restrict__ a_re,
                                                      const double* __restrict__ a_im,
                                                      const double* __restrict__ L,
@@ -176,7 +180,7 @@ __global__ __launch_bounds__(OpTile::NT) void k_opbuild(int W, int G, int M,
                                                      double* __restrict__ A_im,
                                                      const int2* __restrict__ blk, int n_rt,
                                                      int n_ct) {
-  using T = OpTile;
+  using T = OpTile<RT_>;
   extern __shared__ double smem[];
   int ct, rt;
   if (!xcd_swizzle(blockIdx.x, n_rt, n_ct, ct, rt)) return;
@@ -695,12 +699,13 @@ hipError_t onebody_p(SysDev& s, const double* in_re, const double* in_im, double
   return hipGetLastError();
 }
 
-hipError_t opbuild_fp64(SysDev& s, hipStream_t st) {
-  using T = OpTile;
+template <int RT_>
+hipError_t opbuild_rt(SysDev& s, hipStream_t st) {
+  using T = OpTile<RT_>;
   constexpr size_t lds = pipe_lds_bytes<T::WR, T::WC, T::RT, T::CT, 0>();
   static bool lds_ok = false;
   if (!lds_ok) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_opbuild<RT_>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     lds_ok = true;
@@ -708,9 +713,13 @@ hipError_t opbuild_fp64(SysDev& s, hipStream_t st) {
   if (!s.op_blk || s.n_op_blk < 1) return hipErrorInvalidValue;
   const int n_rt = (2 * s.W + T::ROWS - 1) / T::ROWS;
   const int n_ct = s.n_op_blk;
-  hipLaunchKernelGGL(k_opbuild, dim3(xcd_grid(n_ct, n_rt)), dim3(T::NT), lds, st, s.W, s.G,
+  hipLaunchKernelGGL(k_opbuild<RT_>, dim3(xcd_grid(n_ct, n_rt)), dim3(T::NT), lds, st, s.W, s.G,
                      s.M, s.av_re, s.av_im, s.L, s.A_re, s.A_im, s.op_blk, n_rt, n_ct);
   return hipGetLastError();
+}
+
+hipError_t opbuild_fp64(SysDev& s, hipStream_t st) {
+  return 2 * s.W >= 512 ? opbuild_rt<4>(s, st) : opbuild_rt<2>(s, st);
 }
 
 }  // namespace
