@@ -141,29 +141,38 @@ __global__ __launch_bounds__(256) void k_force_bias(int G, int G1, double sqt,
 }
 
 // ---------------------------------------------------------------- small dense
-// Per-walker N x N work in LDS.  Tile engine with up to 160 x 160 outputs.
+// Per-walker N x N work in LDS.  Tile engine of four waves with up to
+// 32 T x 32 T outputs: T = 4 (128 x 128) while 2N <= 128, else T = 5; the
+// smaller stage and accumulator set let two workgroups share a compute unit.
+// The products accumulate over k in the same order for either T.
 
-constexpr int SM_MT = 5, SM_NT = 5;
-constexpr int SM_ROWS = 32 * SM_MT, SM_COLS = 32 * SM_NT;
-constexpr int SM_STAGE = (SM_ROWS + SM_COLS) * kLDK;
+template <int T>
+struct Sm {
+  static constexpr int MT = T, NT = T;
+  static constexpr int ROWS = 32 * T, COLS = 32 * T;
+  static constexpr int STAGE = (ROWS + COLS) * kLDK;
+};
+constexpr int kSmRowsMax = Sm<5>::ROWS;
+__host__ __device__ inline int sm_tiles(int N) { return 2 * N <= Sm<4>::ROWS ? 4 : 5; }
 
 // C[r][c] = sum_k X(r, k) Y(c, k) over k < K; store(r, c, value) is called once
 // per output element (r < nr, c < nc).  Ends with a workgroup barrier.
-template <class GX, class GY, class ST>
+template <int T, class GX, class GY, class ST>
 AFQ_DEV void small_gram(int nr, int nc, int K, GX gx, GY gy, ST store, double* stage) {
+  using E = Sm<T>;
   double* As = stage;
-  double* Bs = stage + SM_ROWS * kLDK;
-  const WaveSplit ws = wave_split<SM_MT, SM_NT>(nr, nc);
-  TileAcc<SM_MT, SM_NT> acc;
+  double* Bs = stage + E::ROWS * kLDK;
+  const WaveSplit ws = wave_split<E::MT, E::NT>(nr, nc);
+  TileAcc<E::MT, E::NT> acc;
   acc.zero();
-  auto fa = [&](int k0, double* S) { stage_rows<SM_ROWS>(S, k0, K, nr, gx); };
-  auto fb = [&](int k0, double* S) { stage_rows<SM_COLS>(S, k0, K, nc, gy); };
-  tile_gemm<SM_MT, SM_NT>(K, ws, fa, fb, As, Bs, acc);
+  auto fa = [&](int k0, double* S) { stage_rows<E::ROWS>(S, k0, K, nr, gx); };
+  auto fb = [&](int k0, double* S) { stage_rows<E::COLS>(S, k0, K, nc, gy); };
+  tile_gemm<E::MT, E::NT>(K, ws, fa, fb, As, Bs, acc);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < SM_MT; ++i)
+  for (int i = 0; i < E::MT; ++i)
 #pragma unroll
-    for (int j = 0; j < SM_NT; ++j) {
+    for (int j = 0; j < E::NT; ++j) {
       if (i >= ws.mtv || j >= ws.ntv) continue;
       const int c = acc_col(ws, j);
 #pragma unroll
@@ -177,10 +186,12 @@ AFQ_DEV void small_gram(int nr, int nc, int K, GX gx, GY gy, ST store, double* s
 
 // out[j][p] = sum_i X[i][j] in[i][p] (complex, X in LDS as X[(i*N + j)*2 + {0,1}]).
 // in and out are planar [N][M] arrays of one walker; out may alias in.
+template <int T>
 AFQ_DEV void apply_right(int N, int M, const double* Xl, const double* in_re, const double* in_im,
                          double* out_re, double* out_im, double* stage) {
+  using E = Sm<T>;
   double* As = stage;
-  double* Bs = stage + SM_ROWS * kLDK;
+  double* Bs = stage + E::ROWS * kLDK;
   const int nr = 2 * N, K = 2 * N;
   auto gx = [&](int r, int k) {
     const int pl = r >= N, j = pl ? r - N : r;
@@ -189,22 +200,22 @@ AFQ_DEV void apply_right(int N, int M, const double* Xl, const double* in_re, co
     if (!pl) return pk ? -xi : xr;
     return pk ? xr : xi;
   };
-  for (int p0 = 0; p0 < M; p0 += SM_COLS) {
-    const int nc = min(SM_COLS, M - p0);
-    const WaveSplit ws = wave_split<SM_MT, SM_NT>(nr, nc);
-    TileAcc<SM_MT, SM_NT> acc;
+  for (int p0 = 0; p0 < M; p0 += E::COLS) {
+    const int nc = min(E::COLS, M - p0);
+    const WaveSplit ws = wave_split<E::MT, E::NT>(nr, nc);
+    TileAcc<E::MT, E::NT> acc;
     acc.zero();
     auto gy = [&](int c, int k) {
       const int pk = k >= N, i = pk ? k - N : k;
       return pk ? in_im[(int64_t)i * M + p0 + c] : in_re[(int64_t)i * M + p0 + c];
     };
-    auto fa = [&](int k0, double* S) { stage_rows<SM_ROWS>(S, k0, K, nr, gx); };
-    auto fb = [&](int k0, double* S) { stage_rows_kmajor<SM_COLS>(S, k0, K, nc, gy); };
-    tile_gemm<SM_MT, SM_NT>(K, ws, fa, fb, As, Bs, acc);
+    auto fa = [&](int k0, double* S) { stage_rows<E::ROWS>(S, k0, K, nr, gx); };
+    auto fb = [&](int k0, double* S) { stage_rows_kmajor<E::COLS>(S, k0, K, nc, gy); };
+    tile_gemm<E::MT, E::NT>(K, ws, fa, fb, As, Bs, acc);
 #pragma unroll
-    for (int i = 0; i < SM_MT; ++i)
+    for (int i = 0; i < E::MT; ++i)
 #pragma unroll
-      for (int j = 0; j < SM_NT; ++j) {
+      for (int j = 0; j < E::NT; ++j) {
         if (i >= ws.mtv || j >= ws.ntv) continue;
         const int c = acc_col(ws, j);
 #pragma unroll
@@ -319,13 +330,14 @@ AFQ_DEV bool all_finite_block(bool v, double* red) {
 }
 
 // O = Psi_T^T Phi, log det O, Theta = Phi O^-1 of walker w (one block).
+template <int T>
 AFQ_DEV void overlap_one(int N, int M, const double* __restrict__ psit,
                          const double* __restrict__ ph_re, const double* __restrict__ ph_im,
                          double* __restrict__ logdet_out, double* __restrict__ th_re,
                          double* __restrict__ th_im, int* __restrict__ bad,
                          double* __restrict__ oinv_out, int w, double* smem) {
   double* stage = smem;
-  double* X = stage + SM_STAGE;             // N x N complex
+  double* X = stage + Sm<T>::STAGE;         // N x N complex
   double* fcol = X + 2 * N * N;             // 2N
   double* red = fcol + 2 * N;               // 8
   int* perm = (int*)(red + 8);              // N
@@ -339,14 +351,14 @@ AFQ_DEV void overlap_one(int N, int M, const double* __restrict__ psit,
     const int pl = c >= N, j = pl ? c - N : c;
     X[(r * N + j) * 2 + pl] = v;
   };
-  small_gram(N, 2 * N, M, gx, gy, st, stage);
+  small_gram<T>(N, 2 * N, M, gx, gy, st, stage);
   cplx ld;
   int ok;
   gj_inverse(N, X, fcol, perm, red, &ld, &ok);
   __syncthreads();
   if (oinv_out)
     for (int e = threadIdx.x; e < 2 * N * N; e += blockDim.x) oinv_out[(int64_t)w * 2 * N * N + e] = X[e];
-  apply_right(N, M, X, pr, pi, th_re + off, th_im + off, stage);
+  apply_right<T>(N, M, X, pr, pi, th_re + off, th_im + off, stage);
   __threadfence();
   __syncthreads();
   bool fin = isfinite(ld.re) && isfinite(ld.im) && ok;
@@ -360,6 +372,7 @@ AFQ_DEV void overlap_one(int N, int M, const double* __restrict__ psit,
   }
 }
 
+template <int T>
 __global__ __launch_bounds__(256) void k_overlap(int N, int M, const double* __restrict__ psit,
                                                  const double* __restrict__ ph_re,
                                                  const double* __restrict__ ph_im,
@@ -369,7 +382,8 @@ __global__ __launch_bounds__(256) void k_overlap(int N, int M, const double* __r
                                                  int* __restrict__ bad,
                                                  double* __restrict__ oinv_out) {
   extern __shared__ double smem[];
-  overlap_one(N, M, psit, ph_re, ph_im, logdet_out, th_re, th_im, bad, oinv_out, blockIdx.x, smem);
+  overlap_one<T>(N, M, psit, ph_re, ph_im, logdet_out, th_re, th_im, bad, oinv_out, blockIdx.x,
+                 smem);
 }
 
 // ---------------------------------------------------------------- weights
@@ -425,11 +439,12 @@ __global__ void k_weight(int W, double tau, double spin, const E0Dev* __restrict
 // qr_logr[w] = sum over passes of sum_j log R_jj (so log det(Psi_T^T Phi)
 // drops by qr_logr).  A failed factorisation marks the walker bad.
 // Factorisation of walker w (one block); the caller skips frozen and bad walkers.
+template <int T>
 AFQ_DEV void qr_one(int N, int M, double* __restrict__ ph_re, double* __restrict__ ph_im,
                     double* __restrict__ qr_logr, int* __restrict__ bad, int w, int64_t sw,
                     double* smem) {
   double* stage = smem;
-  double* S = stage + SM_STAGE;           // N x N complex: S, then R, then R^-1
+  double* S = stage + Sm<T>::STAGE;       // N x N complex: S, then R, then R^-1
   double* col = S + 2 * N * N;            // 2N
   double* fail = col + 2 * N;             // failure flag of the factorisation
   const int64_t off = (int64_t)w * sw;   // walker stride (N M for the walker store)
@@ -456,7 +471,7 @@ AFQ_DEV void qr_one(int N, int M, double* __restrict__ ph_re, double* __restrict
       const int pl = r >= N, i = pl ? r - N : r;
       S[(i * N + c) * 2 + pl] = v;
     };
-    small_gram(2 * N, N, 2 * M, gx, gy, st, stage);
+    small_gram<T>(2 * N, N, 2 * M, gx, gy, st, stage);
     if (pass == 0) {
       double tr = 0.0;
       for (int j = 0; j < N; ++j) tr += S[(j * N + j) * 2];
@@ -521,7 +536,7 @@ AFQ_DEV void qr_one(int N, int M, double* __restrict__ ph_re, double* __restrict
       if (tid == 0) S[(j * N + j) * 2] = rjj;
       __syncthreads();
     }
-    apply_right(N, M, S, pr, pi, pr, pi, stage);
+    apply_right<T>(N, M, S, pr, pi, pr, pi, stage);
     __threadfence();
     __syncthreads();
   }
@@ -538,6 +553,7 @@ AFQ_DEV bool qr_due(const CallState* cs, int add, int every) {
   return every > 0 && (t + 1) % (uint64_t)every == 0;
 }
 
+template <int T>
 __global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ ph_re,
                                             double* __restrict__ ph_im,
                                             double* __restrict__ qr_logr,
@@ -553,7 +569,7 @@ __global__ __launch_bounds__(256) void k_qr(int N, int M, double* __restrict__ p
     return;
   }
   if (!alive[w] || bad[w]) return;
-  qr_one(N, M, ph_re, ph_im, qr_logr, bad, w, sw, smem);
+  qr_one<T>(N, M, ph_re, ph_im, qr_logr, bad, w, sw, smem);
 }
 
 // Frozen walkers keep their held state: copy it over the proposed one.
@@ -625,13 +641,22 @@ __global__ __launch_bounds__(256) void k_back_queue(const BackSys* __restrict__ 
     const int2 d = items[it];
     const BackSys& S = sys[d.x];
     const int w = d.y;
-    overlap_one(S.N, S.M, S.psit, S.phn_re, S.phn_im, S.logdet_n, S.thn_re, S.thn_im, S.bad,
-                nullptr, w, smem);
+    if (sm_tiles(S.N) == 4)
+      overlap_one<4>(S.N, S.M, S.psit, S.phn_re, S.phn_im, S.logdet_n, S.thn_re, S.thn_im, S.bad,
+                     nullptr, w, smem);
+    else
+      overlap_one<5>(S.N, S.M, S.psit, S.phn_re, S.phn_im, S.logdet_n, S.thn_re, S.thn_im, S.bad,
+                     nullptr, w, smem);
     __syncthreads();
     if (due) {
       if (threadIdx.x == 0) run = S.alive[w] && !S.bad[w];
       __syncthreads();
-      if (run) qr_one(S.N, S.M, S.phn_re, S.phn_im, S.qr_logr, S.bad, w, (int64_t)S.N * S.M, smem);
+      if (run) {
+        if (sm_tiles(S.N) == 4)
+          qr_one<4>(S.N, S.M, S.phn_re, S.phn_im, S.qr_logr, S.bad, w, (int64_t)S.N * S.M, smem);
+        else
+          qr_one<5>(S.N, S.M, S.phn_re, S.phn_im, S.qr_logr, S.bad, w, (int64_t)S.N * S.M, smem);
+      }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -904,10 +929,11 @@ __global__ void k_pack_complex(const double* __restrict__ re, const double* __re
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+int sm_stage(int N) { return sm_tiles(N) == 4 ? Sm<4>::STAGE : Sm<5>::STAGE; }
 size_t overlap_lds(int N) {
-  return sizeof(double) * (SM_STAGE + 2 * N * N + 2 * N + 8) + sizeof(int) * N;
+  return sizeof(double) * (sm_stage(N) + 2 * N * N + 2 * N + 8) + sizeof(int) * N;
 }
-size_t qr_lds(int N) { return sizeof(double) * (SM_STAGE + 2 * N * N + 2 * N + 1); }
+size_t qr_lds(int N) { return sizeof(double) * (sm_stage(N) + 2 * N * N + 2 * N + 1); }
 
 // Allow a kernel the whole 160 KiB of LDS of a gfx950 CU (once per kernel).
 hipError_t allow_full_lds(const void* fn, bool& done) {
@@ -916,7 +942,26 @@ hipError_t allow_full_lds(const void* fn, bool& done) {
   if (e == hipSuccess) done = true;
   return e;
 }
-bool g_lds_overlap = false, g_lds_qr = false;
+bool g_lds_overlap[2] = {false, false}, g_lds_qr[2] = {false, false};
+
+// k_qr<T> over all walkers of a system (strides sw between walkers).
+hipError_t run_qr(const SysDev& s, double* ph_re, double* ph_im, double* logr, int* bad,
+                  const CallState* cs, int add, int every, int64_t sw, hipStream_t st) {
+  if (2 * s.N > kSmRowsMax) return hipErrorInvalidValue;
+  const size_t lds = qr_lds(s.N);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const bool t4 = sm_tiles(s.N) == 4;
+  const void* fn = t4 ? (const void*)k_qr<4> : (const void*)k_qr<5>;
+  hipError_t e = allow_full_lds(fn, g_lds_qr[t4 ? 0 : 1]);
+  if (e != hipSuccess) return e;
+  if (t4)
+    hipLaunchKernelGGL(k_qr<4>, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, logr, bad,
+                       s.alive, cs, add, every, sw);
+  else
+    hipLaunchKernelGGL(k_qr<5>, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, logr, bad,
+                       s.alive, cs, add, every, sw);
+  return hipGetLastError();
+}
 
 }  // namespace
 
@@ -978,13 +1023,19 @@ hipError_t launch_force_bias(SysDev& s, const double* x, double tau, hipStream_t
 hipError_t launch_overlap(SysDev& s, int W, const double* ph_re, const double* ph_im,
                           double* logdet_out, double* th_re, double* th_im, int* bad,
                           hipStream_t st) {
-  if (2 * s.N > SM_ROWS) return hipErrorInvalidValue;
+  if (2 * s.N > kSmRowsMax) return hipErrorInvalidValue;
   const size_t lds = overlap_lds(s.N);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = allow_full_lds((const void*)k_overlap, g_lds_overlap);
+  const bool t4 = sm_tiles(s.N) == 4;
+  const void* fn = t4 ? (const void*)k_overlap<4> : (const void*)k_overlap<5>;
+  hipError_t e = allow_full_lds(fn, g_lds_overlap[t4 ? 0 : 1]);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_overlap, dim3(W), dim3(256), lds, st, s.N, s.M, s.psit, ph_re, ph_im,
-                     logdet_out, th_re, th_im, bad, (double*)nullptr);
+  if (t4)
+    hipLaunchKernelGGL(k_overlap<4>, dim3(W), dim3(256), lds, st, s.N, s.M, s.psit, ph_re, ph_im,
+                       logdet_out, th_re, th_im, bad, (double*)nullptr);
+  else
+    hipLaunchKernelGGL(k_overlap<5>, dim3(W), dim3(256), lds, st, s.N, s.M, s.psit, ph_re, ph_im,
+                       logdet_out, th_re, th_im, bad, (double*)nullptr);
   return hipGetLastError();
 }
 
@@ -998,26 +1049,12 @@ hipError_t launch_weight(SysDev& s, double tau, const double* qr_logr, hipStream
 
 hipError_t launch_qr(SysDev& s, double* ph_re, double* ph_im, double* qr_logr, hipStream_t st,
                      const CallState* cs, int add, int every) {
-  if (2 * s.N > SM_ROWS) return hipErrorInvalidValue;
-  const size_t lds = qr_lds(s.N);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = allow_full_lds((const void*)k_qr, g_lds_qr);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_qr, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, qr_logr, s.bad,
-                     s.alive, cs, add, every, (int64_t)s.N * s.M);
-  return hipGetLastError();
+  return run_qr(s, ph_re, ph_im, qr_logr, s.bad, cs, add, every, (int64_t)s.N * s.M, st);
 }
 
 hipError_t launch_qr_strided(SysDev& s, double* ph_re, double* ph_im, int64_t sw, double* logr,
                              int* bad, hipStream_t st) {
-  if (2 * s.N > SM_ROWS) return hipErrorInvalidValue;
-  const size_t lds = qr_lds(s.N);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = allow_full_lds((const void*)k_qr, g_lds_qr);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_qr, dim3(s.W), dim3(256), lds, st, s.N, s.M, ph_re, ph_im, logr, bad,
-                     s.alive, (const CallState*)nullptr, 0, 0, sw);
-  return hipGetLastError();
+  return run_qr(s, ph_re, ph_im, logr, bad, nullptr, 0, 0, sw, st);
 }
 
 size_t back_lds(int N) {
@@ -1029,7 +1066,7 @@ hipError_t launch_back_queue(const BackSys* d_sys, const int2* d_items, int n_it
                              WorkQ* q, double tau, const CallState* cs, int add, int every,
                              bool qr_now, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  if (2 * max_n > SM_ROWS) return hipErrorInvalidValue;
+  if (2 * max_n > kSmRowsMax) return hipErrorInvalidValue;
   const size_t work = back_lds(max_n);
   const int ctl_off = (int)((work + 7) / 8);        // in doubles
   const size_t lds = sizeof(double) * (ctl_off + 1);
