@@ -165,6 +165,26 @@ def test_propagation_reorth_schedule_and_large_tau(ctx):
         assert v < C.RTOL, (key, v)
 
 
+@pytest.mark.parametrize("shape,method", [((163, 80, 40), O.EXP_KRYLOV),
+                                          ((150, 67, 30), O.EXP_TAYLOR)])
+def test_propagation_widest_orbital_blocks(ctx, shape, method):
+    """The largest N the kernels take (80: 2N = 160 rows, ten row tiles of
+    the operator-orbital product, the 160 x 160 per-walker engine) and a
+    nine-tile case, with M not a multiple of 4 (the products' groups of four
+    q then straddle the re/im halves of K differently from a plain sum):
+    2 of 6 walkers tracked over 4 steps, QR every 2 steps; couplings scaled
+    by 1/sqrt(M) as in the production shapes."""
+    M, N, G = shape
+    s = 1.0 / np.sqrt(M)
+    case = C.Case.random(M, N, G, seed=M + N, sigma_h=0.1 * s, sigma_A=0.05 * s)
+    worst, flagged, sid = C.run_pair(case, ctx, tau=0.05, k=6, method=method, reorth=2,
+                                     n_steps=4, n_walkers=6, track=[0, 5])
+    print("widest", shape, method, worst, "flagged", sorted(flagged))
+    assert len(flagged) <= 1
+    for key, v in worst.items():
+        assert v < C.RTOL, (key, v)
+
+
 def test_batch_independence_bitwise(ctx):
     """A batch of 12 walkers equals a batch of its first 5, bitwise, for the
     same fields (walkers do not interact)."""
