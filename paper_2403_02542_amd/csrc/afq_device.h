@@ -249,13 +249,9 @@ AFQ_DEV void stage_rows_kmajor(double* S, int k0, int K, int nvalid, Get get) {
 // stages: chunk c+1 is fetched from global memory into registers while the
 // MFMAs of chunk c run, then stored into the other stage (one barrier per
 // chunk).  A_KM / B_KM: the operand is stored k-major (consecutive r
-// contiguous); consecutive threads then walk r instead of k.  gn(r, k), if
-// given, negates element (r, k) of the row operand when it is staged: the
-// getters then return plain loads, so that nothing waits for a prefetch
-// before the chunk's MFMAs have been issued.
-struct PipeNoNeg {
-  AFQ_DEV bool operator()(int, int) const { return false; }
-};
+// contiguous); consecutive threads then walk r instead of k.  The getters
+// should return plain loads: arithmetic on a loaded value makes the compiler
+// wait for that prefetch before the chunk's MFMAs are issued.
 
 template <int WR, int WC, int RT, int CT, int BK = 16>
 struct Pipe {
@@ -274,10 +270,9 @@ struct PipeSplit {
   int rt0, mtv, ct0, ntv;
 };
 
-template <int WR, int WC, int RT, int CT, bool A_KM, bool B_KM, int BK = 16, class GA, class GB,
-          class GN = PipeNoNeg>
+template <int WR, int WC, int RT, int CT, bool A_KM, bool B_KM, int BK = 16, class GA, class GB>
 AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
-                            d4_t (&acc)[RT][CT], GN gn = GN()) {
+                            d4_t (&acc)[RT][CT]) {
   using P = Pipe<WR, WC, RT, CT, BK>;
   constexpr int LDK = P::LDK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -336,15 +331,14 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
       pf[i] = v;
     }
   };
-  auto store = [&](double* S, int k0) {
+  auto store = [&](double* S) {
 #pragma unroll
     for (int i = 0; i < P::PF; ++i) {
       const int e = tid + i * P::NT;
       if (e < P::TOT) {
         int row, k;
         slot(e, row, k);
-        const double x = pf[i];
-        S[row * LDK + k] = (row < P::ROWS && gn(row, k0 + k)) ? -x : x;
+        S[row * LDK + k] = pf[i];
       }
     }
   };
@@ -355,7 +349,7 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
   // products are discarded by the caller's bounds)
   const bool full = sp.mtv > 0 && sp.ntv > 0;
   fetch(0);
-  store(smem, 0);
+  store(smem);
   __syncthreads();
   for (int ch = 0; ch < nchunk; ++ch) {
     const double* As = smem + (ch & 1) * P::STAGE;
@@ -395,7 +389,7 @@ AFQ_DEV PipeSplit pipe_gemm(int K, int nr, int nc, GA ga, GB gb, double* smem,
         }
       }
     }
-    if (ch + 1 < nchunk) store(smem + ((ch + 1) & 1) * P::STAGE, (ch + 1) * BK);
+    if (ch + 1 < nchunk) store(smem + ((ch + 1) & 1) * P::STAGE);
     __syncthreads();
   }
   return sp;
@@ -658,12 +652,11 @@ AFQ_DEV void pipe_emit(const PipeSplit& sp, f4_t (&acc)[RT][CT], F f) {
 // C tile of the FP64 engine (PC = 0) or of the BF16-split engine with PC
 // pieces, then f(row, col, value) for every element.
 template <int WR, int WC, int RT, int CT, int PC, bool A_KM, bool B_KM, int BK = 16, class GA,
-          class GB, class F, class GN = PipeNoNeg>
-AFQ_DEV void pipe_run(int K, int nr, int nc, GA ga, GB gb, double* smem, F f, GN gn = GN()) {
+          class GB, class F>
+AFQ_DEV void pipe_run(int K, int nr, int nc, GA ga, GB gb, double* smem, F f) {
   if constexpr (PC == 0) {
     d4_t acc[RT][CT];
-    const PipeSplit sp =
-        pipe_gemm<WR, WC, RT, CT, A_KM, B_KM, BK>(K, nr, nc, ga, gb, smem, acc, gn);
+    const PipeSplit sp = pipe_gemm<WR, WC, RT, CT, A_KM, B_KM, BK>(K, nr, nc, ga, gb, smem, acc);
     pipe_emit(sp, acc, f);
   } else {
     f4_t acc[RT][CT];
