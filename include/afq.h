@@ -90,12 +90,19 @@ afq_status afq_init_hamiltonian(afq_ctx* ctx, int64_t M, int64_t n_chol,
                                 const double* h, const double* L, double e_core,
                                 int ptr_is_device, int32_t* sys_id);
 
-/* Trial determinant Psi_T (Sec. II.A): M x n_alpha real, orthonormal
- * columns (checked to 1e-10), row-major, host or device memory (copied).
- * Closed shell: n_beta must equal n_alpha, and the alpha and beta blocks of
- * every walker are equal, so each trace of Eqs. eloc, hyben and force_shift
- * carries a spin factor 2 (AFQ_EINVAL otherwise, naming
- * afq_init_trial_spin_orbital).  Precomputes the mean-field shift Lbar_g
+/* Trial determinant Psi_T (Sec. II.A), row-major, host or device memory
+ * (copied), columns orthonormal (checked to 1e-10).
+ * Closed shell (n_beta == n_alpha): Psi_T is M x n_alpha; the alpha and
+ * beta blocks of every walker are equal, so each trace of Eqs. eloc, hyben
+ * and force_shift carries a spin factor 2.
+ * Open shell (n_beta != n_alpha, either may be 0): Psi_T is
+ * M x (n_alpha + n_beta), the alpha orbitals then the beta orbitals (each
+ * set orthonormal; a UHF determinant).  The system is then rewritten in
+ * the 2M spin orbitals as for afq_init_trial_spin_orbital (h and L_g become
+ * diag(X, X) on the device, 4x their memory; 2M <= 512, n_alpha + n_beta <=
+ * 80) and every later call sees M' = 2M and N = n_alpha + n_beta.  A trial
+ * with equal counts but separate alpha and beta orbitals goes through
+ * afq_init_trial_spin_orbital.  Precomputes the mean-field shift Lbar_g
  * (Eq. force_shift), the one-body matrix H1 = h - 1/2 sum_g L_g L_g +
  * sum_g Lbar_g L_g that accompanies the shifted HS transform, its
  * eigendecomposition for the exact half-step exp(-tau H1/2) of Sec. III.B,
@@ -104,8 +111,9 @@ afq_status afq_init_hamiltonian(afq_ctx* ctx, int64_t M, int64_t n_chol,
 afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha,
                           int64_t n_beta, const double* psi_t, int ptr_is_device);
 
-/* Open-shell trial (any N_alpha, N_beta, including a UHF determinant): the
- * system's M basis functions are spin orbitals (for a spatial Hamiltonian
+/* Trial of one determinant of spin orbitals (any N_alpha, N_beta, including
+ * a UHF or a general determinant): the system's M basis functions are spin
+ * orbitals (for a spatial Hamiltonian
  * (h, L) of M/2 orbitals, h and every L_g block-diagonal diag(X, X)) and
  * Psi_T is one M x n_elec determinant of spin orbitals (for (Psi_a, Psi_b)
  * the block-diagonal diag(Psi_a, Psi_b), n_elec = N_alpha + N_beta).  The

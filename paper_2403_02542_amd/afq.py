@@ -231,11 +231,23 @@ class Context:
         return sid.value
 
     def init_trial(self, sys_id: int, psi_t, n_beta=None):
+        """Closed shell (n_beta None): psi_t is M x N, both spins.  Open shell:
+        psi_t is M x (N_alpha + N_beta), the alpha orbitals then the beta
+        ones, with N_alpha != N_beta; the library then works in 2M spin
+        orbitals (walkers 2M x (N_alpha + N_beta))."""
         p, dev, keep = _arg(psi_t, np.float64)
-        N = psi_t.shape[1]
-        self._check(self._lib.afq_init_trial(self._h, sys_id, N, N if n_beta is None else n_beta,
-                                             p, dev))
-        self.dims[sys_id]["N"] = N
+        cols = psi_t.shape[1]
+        if n_beta is None:
+            n_alpha = n_beta = cols
+        else:
+            n_alpha = cols - n_beta
+            if n_alpha == n_beta:
+                raise ValueError("equal N_alpha and N_beta with separate orbitals: embed the "
+                                 "system in spin orbitals and use init_trial_spin_orbital")
+        self._check(self._lib.afq_init_trial(self._h, sys_id, n_alpha, n_beta, p, dev))
+        self.dims[sys_id]["N"] = cols
+        if n_alpha != n_beta:
+            self.dims[sys_id]["M"] *= 2
 
     def init_trial_spin_orbital(self, sys_id: int, psi_t):
         """One determinant of spin orbitals (spin factor 1); the system's

@@ -1169,18 +1169,103 @@ afq_status init_trial(afq_ctx* ctx, SysDev& s, int32_t sys_id, int N, double spi
 
 }  // namespace
 
+namespace {
+
+// nb matrices of M x M into nb block-diagonal matrices diag(X, X) of 2M x 2M.
+__global__ void k_embed_spin(int64_t nb, int M, const double* __restrict__ src,
+                             double* __restrict__ dst) {
+  const int64_t M2 = 2 * (int64_t)M, per = M2 * M2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nb * per;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / per, r = e - b * per;
+    const int64_t p = r / M2, q = r - p * M2;
+    double v = 0.0;
+    if ((p < M) == (q < M)) v = src[b * M * M + (p % M) * M + (q % M)];
+    dst[e] = v;
+  }
+}
+
+afq_status dfree(std::vector<void*>& owner, void* p) {
+  for (size_t i = 0; i < owner.size(); ++i)
+    if (owner[i] == p) {
+      (void)hipFree(p);
+      owner.erase(owner.begin() + (std::ptrdiff_t)i);
+      return AFQ_OK;
+    }
+  return AFQ_EINVAL;
+}
+
+// Columns [c0, c0 + n) of the row-major M x ld matrix psi orthonormal to 1e-10.
+bool orthonormal_cols(const std::vector<double>& psi, int M, int ld, int c0, int n) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double d = 0.0;
+      for (int p = 0; p < M; ++p) d += psi[(size_t)p * ld + c0 + i] * psi[(size_t)p * ld + c0 + j];
+      if (!(std::fabs(d - (i == j ? 1.0 : 0.0)) <= 1e-10)) return false;
+    }
+  return true;
+}
+
+// Open shell from spatial orbitals: the system is rewritten in the 2M spin
+// orbitals (h and every L_g as diag(X, X), built on the device; the M-basis
+// copies are freed) and the trial becomes diag(Psi_a, Psi_b), spin factor 1.
+afq_status init_trial_open_shell(afq_ctx* ctx, SysDev& s, int32_t sys_id, int na, int nb,
+                                 const double* psi_t, int ptr_is_device) {
+  const int M = s.M, N = na + nb, G = s.G;
+  std::vector<double> psi((size_t)M * N);
+  if (ptr_is_device) {
+    HIPCHK(hipMemcpyAsync(psi.data(), psi_t, psi.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  } else {
+    std::memcpy(psi.data(), psi_t, psi.size() * 8);
+  }
+  if (!orthonormal_cols(psi, M, N, 0, na) || !orthonormal_cols(psi, M, N, na, nb))
+    return fail(ctx, AFQ_EINVAL, "psi_t: the alpha or the beta columns are not orthonormal");
+  const int M2 = 2 * M;
+  std::vector<double> psi2((size_t)M2 * N, 0.0);
+  for (int p = 0; p < M; ++p) {
+    for (int i = 0; i < na; ++i) psi2[(size_t)p * N + i] = psi[(size_t)p * N + i];
+    for (int i = na; i < N; ++i) psi2[(size_t)(M + p) * N + i] = psi[(size_t)p * N + i];
+  }
+  auto& own = ctx->sys_allocs[sys_id];
+  double *h2, *L2;
+  TRY(dalloc(ctx, own, &h2, (size_t)M2 * M2));
+  TRY(dalloc(ctx, own, &L2, (size_t)M2 * M2 * G));
+  const int64_t n2 = (int64_t)M2 * M2 * G;
+  const unsigned grid = (unsigned)std::min<int64_t>((n2 + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_embed_spin, dim3(grid), dim3(256), 0, ctx->stream, (int64_t)1, M, s.h, h2);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_embed_spin, dim3(grid), dim3(256), 0, ctx->stream, (int64_t)G, M, s.L, L2);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  (void)dfree(own, s.h);
+  (void)dfree(own, s.L);
+  s.h = h2;
+  s.L = L2;
+  s.M = M2;
+  return init_trial(ctx, s, sys_id, N, 1.0, psi2.data(), 0);
+}
+
+}  // namespace
+
 afq_status afq_init_trial(afq_ctx* ctx, int32_t sys_id, int64_t n_alpha, int64_t n_beta,
                           const double* psi_t, int ptr_is_device) try {
   SysDev* sp;
   TRY(get_sys(ctx, sys_id, &sp));
   if (!psi_t) return fail(ctx, AFQ_EINVAL, "null psi_t");
-  if (n_alpha != n_beta)
-    return fail(ctx, AFQ_EINVAL,
-                "n_alpha != n_beta: write the system in spin orbitals and use "
-                "afq_init_trial_spin_orbital");
+  if (sp->trial_ready) return fail(ctx, AFQ_ESTATE, "trial already set for this system");
+  if (n_alpha != n_beta) {
+    if (n_alpha < 0 || n_beta < 0 || n_alpha > sp->M || n_beta > sp->M ||
+        n_alpha + n_beta > 80)
+      return fail(ctx, AFQ_EINVAL,
+                  "open shell: n_alpha and n_beta in [0, M], n_alpha + n_beta <= 80");
+    if (2 * sp->M > 512) return fail(ctx, AFQ_EINVAL, "open shell: 2M must be <= 512");
+    HIPCHK(hipSetDevice(ctx->device));
+    return init_trial_open_shell(ctx, *sp, sys_id, (int)n_alpha, (int)n_beta, psi_t,
+                                 ptr_is_device);
+  }
   if (n_alpha < 1 || n_alpha > sp->M || n_alpha > 80)
     return fail(ctx, AFQ_EINVAL, "n_alpha must be in [1, min(M, 80)]");
-  if (sp->trial_ready) return fail(ctx, AFQ_ESTATE, "trial already set for this system");
   HIPCHK(hipSetDevice(ctx->device));
   return init_trial(ctx, *sp, sys_id, (int)n_alpha, 2.0, psi_t, ptr_is_device);
 } catch (...) {

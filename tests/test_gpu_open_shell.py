@@ -1,6 +1,7 @@
 """GPU parity of open-shell walkers (spin-orbital determinants, spin factor
 1 in Eqs. eloc, hyben and force_shift) against the oracle, through the
-C ABI: an N_alpha = 5, N_beta = 3 system propagated step by step, the
+C ABI: an N_alpha = 5, N_beta = 3 system propagated step by step (set up
+from spatial orbitals by afq_init_trial as well), the
 spin-orbital embedding of a closed-shell system against the closed-shell
 path, the BF16-split local energy on spin orbitals, and the many-system
 graph schedule with a closed-shell and an open-shell system together."""
@@ -145,12 +146,49 @@ def test_open_and_closed_shell_in_one_graph_batch():
             assert np.array_equal(a[key], b[key]), key
 
 
+def test_open_shell_trial_from_spatial_orbitals(ctx):
+    """afq_init_trial with N_alpha = 5 != N_beta = 3 and Psi_T = [Psi_a, Psi_b]
+    over the 24 spatial orbitals rewrites the system in spin orbitals on the
+    device: the run equals, bitwise, the same system embedded on the host and
+    set up with afq_init_trial_spin_orbital, on the same fields."""
+    import torch
+    M, G, na, nb = 24, 60, 5, 3
+    ham = W.hamiltonian(M, G, 0.1, 0.3 / np.sqrt(M), 21, 0.0)
+    pa = W.rhf_trial(ham.h, ham.L, na, n_iter=3)
+    pb = pa[:, :nb]
+    h2, L2, psi2 = W.spin_orbital_system(ham.h, ham.L, pa, pb)
+    nw = 16
+    sa = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+    ctx.init_trial(sa, np.hstack([pa, pb]), n_beta=nb)
+    ctx.init_walkers(sa, nw)
+    sb = ctx.init_hamiltonian(h2, L2, ham.e_core)
+    ctx.init_trial_spin_orbital(sb, psi2)
+    ctx.init_walkers(sb, nw)
+    assert ctx.get_e0(sa) == ctx.get_e0(sb)
+    for s in range(6):
+        x = C.to_dev(W.fields(0, 0, s, nw, G))
+        for sid in (sa, sb):
+            ctx.propagate_batch(sid, tau=0.05, n_steps=1, exp_order=6, reorth_every=2, step0=s,
+                                fields=x)
+        torch.cuda.synchronize()
+        a, b = ctx.get_walkers(sa), ctx.get_walkers(sb)
+        assert a["phi"].shape == (nw, 2 * M, na + nb)
+        for key in ("phi", "weight", "log_ovlp"):
+            assert np.array_equal(a[key], b[key]), (s, key)
+        assert np.array_equal(ctx.local_energy_batch(sa), ctx.local_energy_batch(sb)), s
+
+
 def test_open_shell_arguments(ctx):
     from paper_2403_02542_amd import afq
     case = C.Case.from_config("c1")
     sid = ctx.init_hamiltonian(case.h, case.L, case.e_core)
+    # equal counts with separate orbitals are the spin-orbital entry point's
+    with pytest.raises(ValueError):
+        ctx.init_trial(sid, np.hstack([case.psi, case.psi]), n_beta=case.N)
+    # the beta columns must be orthonormal among themselves
+    bad = np.hstack([case.psi, 2.0 * case.psi[:, :2]])
     with pytest.raises(afq.AfqError) as e:
-        ctx.init_trial(sid, case.psi, n_beta=case.N - 1)
+        ctx.init_trial(sid, bad, n_beta=2)
     assert e.value.code == afq.EINVAL
     ctx.init_trial_spin_orbital(sid, case.psi)
     with pytest.raises(afq.AfqError) as e:
@@ -160,4 +198,11 @@ def test_open_shell_arguments(ctx):
     with pytest.raises(afq.AfqError) as e:
         ctx.local_energy_adjoint(sid, np.ones(4), np.zeros((case.M, case.M)),
                                  np.zeros((case.G, case.M, case.M)))
+    assert e.value.code == afq.EINVAL
+    # 2M above the kernels' 512
+    M = 300
+    big = ctx.init_hamiltonian(np.diag(np.linspace(-2.0, 0.0, M)), np.zeros((1, M, M)), 0.0)
+    psi = np.eye(M)[:, :3]
+    with pytest.raises(afq.AfqError) as e:
+        ctx.init_trial(big, psi, n_beta=1)
     assert e.value.code == afq.EINVAL
