@@ -100,8 +100,10 @@ afq_status afq_init_hamiltonian(afq_ctx* ctx, int64_t M, int64_t n_chol,
  * set orthonormal; a UHF determinant).  The system is then rewritten in
  * the 2M spin orbitals as for afq_init_trial_spin_orbital (h and L_g become
  * diag(X, X) on the device, 4x their memory; 2M <= 512, n_alpha + n_beta <=
- * 80) and every later call sees M' = 2M and N = n_alpha + n_beta.  A trial
- * with equal counts but separate alpha and beta orbitals goes through
+ * 80) and every later call sees M' = 2M and N = n_alpha + n_beta (an
+ * AFQ_ENOMEM or AFQ_EDEVICE after the rewrite leaves the system in spin
+ * orbitals without a trial: initialise a new system).  A trial with equal
+ * counts but separate alpha and beta orbitals goes through
  * afq_init_trial_spin_orbital.  Precomputes the mean-field shift Lbar_g
  * (Eq. force_shift), the one-body matrix H1 = h - 1/2 sum_g L_g L_g +
  * sum_g Lbar_g L_g that accompanies the shifted HS transform, its
