@@ -228,6 +228,69 @@ def uneven_cpu_baseline(cfgs, nproc):
                       f"wall {wall:.1f} s"}
 
 
+def open_shell_bench(args):
+    """Open-shell walkers beside the closed shell on the same Hamiltonian (the
+    c2 shape: M = 120, G = 600, 256 walkers, Krylov k = 8, tau = 0.05, QR every
+    step): N_alpha = 20, N_beta = 18 through afq_init_trial (the library runs
+    them as one determinant of 2M = 240 spin orbitals), against N = 20 closed
+    shell.  FP64, fields from the library's generator, HIP-event phases."""
+    import torch
+    from paper_2403_02542_amd import afq
+    cfg = W.CONFIGS["c2"]
+    nb = cfg.N - 2
+    log(f"generating workload {cfg.name}")
+    ham, psi = W.make_system(cfg)
+    ctx = afq.Context(0)
+    res = {}
+    for name in ("closed_shell", "open_shell"):
+        sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+        if name == "open_shell":
+            ctx.init_trial(sid, np.hstack([psi, psi[:, :nb]]), n_beta=nb)
+        else:
+            ctx.init_trial(sid, psi)
+        ctx.init_walkers(sid, cfg.W)
+        kw = dict(tau=cfg.tau, exp_method=afq.EXP_KRYLOV, exp_order=cfg.k,
+                  reorth_every=cfg.reorth_every, seed=0)
+        ctx.propagate_batch(sid, n_steps=args.warmup, step0=0, **kw)
+        ctx.sync()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        ctx.propagate_batch(sid, n_steps=args.steps, step0=args.warmup, **kw)
+        ctx.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        d = ctx.dims[sid]
+        Mx, Nx = d["M"], d["N"]
+        ex_ms = prof["exchange"][0] / max(1, prof["exchange"][1])
+        fl = exchange_flops_per_walker(Mx, Nx, cfg.G) * cfg.W
+        res[name] = {"value": cfg.W * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                     "orbitals": Mx, "electrons": Nx,
+                     "local_energy_ms": ex_ms,
+                     "local_energy_frac_fp64_peak": fl / (ex_ms * 1e-3) / PEAK_FP64,
+                     "phases_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()}}
+        log(f"{name}: {res[name]['value']:.1f} walker-steps/s")
+    o, c = res["open_shell"], res["closed_shell"]
+    line = {"metric": "walker-steps/sec, open shell (c2 Hamiltonian, N_alpha=20, N_beta=18, "
+                      "2M = 240 spin orbitals, FP64)",
+            "value": o["value"], "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": o["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic (seeded random Cholesky Hamiltonian, mean-field trial, Philox fields)",
+            "config": {"workload": "c2 Hamiltonian (M=120, G=600), 256 walkers, Krylov k=8, "
+                                   "tau=0.05, QR every step; open shell N_alpha=20, N_beta=18",
+                       "parallelism": "1 GPU"},
+            "open_shell": o, "closed_shell_same_hamiltonian": c,
+            "open_over_closed_time": o["ms_per_step"] / c["ms_per_step"],
+            "note": "spin-orbital form: operator, products and L over 2M functions with half of "
+                    "every matrix zero; separate alpha and beta blocks would do about a quarter "
+                    "to a half of this work"}
+    print(json.dumps(line))
+
+
 def uneven_bench(args):
     """Throughput of the 48-system uneven batch (M ~ U{40..400}, N = M/6,
     G = 5M, 64 walkers each, Krylov k = 8, tau = 0.05, QR every step)."""
@@ -456,6 +519,8 @@ def main():
                          "HBM byte counters of a profiler) and exit")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the adjoint entry points at the c5 shape instead of the step")
+    ap.add_argument("--open-shell", action="store_true",
+                    help="open-shell walkers beside the closed shell on the c2 Hamiltonian")
     ap.add_argument("--uneven", action="store_true",
                     help="time the 48-system uneven batch (c4) instead of the single system")
     ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "streams", "graph"])
@@ -468,6 +533,9 @@ def main():
         return
     if args.uneven and args.gpus == 1:
         uneven_bench(args)
+        return
+    if args.open_shell and args.gpus == 1:
+        open_shell_bench(args)
         return
     if args.copy_probe:
         import torch
