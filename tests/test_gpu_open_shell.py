@@ -50,6 +50,35 @@ def test_open_shell_parity(ctx, prop, method, k):
         assert v < C.RTOL, (key, v)
 
 
+def test_fully_polarised_parity(ctx):
+    """N_alpha = 4, N_beta = 0 (every electron of one spin) set up from the
+    spatial orbitals through afq_init_trial: 16 walkers, all tracked over 8
+    steps against the oracle in spin orbitals."""
+    M, G, na = 20, 40, 4
+    ham = W.hamiltonian(M, G, 0.1, 0.3 / np.sqrt(M), 17, 0.0)
+    pa = W.rhf_trial(ham.h, ham.L, na, n_iter=3)
+    h2, L2, psi2 = W.spin_orbital_system(ham.h, ham.L, pa, pa[:, :0])
+    case = C.Case(h2, L2, psi2, ham.e_core, spin=1)
+    nw = 16
+    sid = ctx.init_hamiltonian(ham.h, ham.L, ham.e_core)
+    ctx.init_trial(sid, pa, n_beta=0)
+    ctx.init_walkers(sid, nw)
+    p = case.oracle(0.05)
+    assert ctx.get_e0(sid) == pytest.approx(p.e0, rel=1e-12)
+    wks = [O.init_walker(p) for _ in range(nw)]
+    import torch
+    for s in range(8):
+        x = W.fields(0, 0, s, nw, G)
+        ctx.propagate_batch(sid, tau=0.05, n_steps=1, exp_order=6, reorth_every=2, step0=s,
+                            fields=C.to_dev(x), e0=p.e0)
+        torch.cuda.synchronize()
+        st = ctx.get_walkers(sid)
+        for w in range(nw):
+            wks[w], info = O.walker_step(p, wks[w], x[w], O.EXP_KRYLOV, 6, O.reorth_due(s, 2))
+            assert C.rel(st["phi"][w], wks[w].phi) < C.RTOL, (s, w)
+            assert abs(st["weight"][w] - wks[w].weight) <= C.RTOL * max(1.0, wks[w].weight), (s, w)
+
+
 def test_closed_shell_embedding_matches_closed_shell(ctx):
     """c1 written in spin orbitals (Psi_a = Psi_b) and run with spin factor 1
     follows the closed-shell run on the same fields: equal weights, E_L and
